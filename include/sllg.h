@@ -1,0 +1,200 @@
+/*
+ * sllg.h - C ABI of the MI355X stochastic-LLG hysteresis-loop library.
+ *
+ * The library integrates the stochastic Landau-Lifshitz-Gilbert equation
+ * (Eq. 1 of Behbahani, Plumer, Saika-Voivod, arXiv:1912.00310) on 3-D grids
+ * of cubic macrospin cells of edge b*a0, with
+ *   - 6-neighbour exchange, free boundaries (material paragraph: A0, J_eff),
+ *   - uniaxial anisotropy along z or per-cell axes in a cone ("5 degree
+ *     dispersion", material paragraph),
+ *   - an applied field along z swept in time (protocol paragraph, SR = 4 Hmax f),
+ *   - Brown's stochastic thermal field (text under Eq. 1),
+ * stepped by the Heun predictor-corrector, and reduces the mean z-component of
+ * the cells' unit magnetisation into dynamic hysteresis loops every step
+ * (the loop ordinate m_H defined after Eq. 1).  Cell parameters follow the
+ * modified Grinstein-Koch rule: A(b) = zeta A0, K(b) = zeta^3 K0 (Eqs. 8-9),
+ * H(b) = zeta H0 (Eq. 10), loops rescaled by 1 - delta(1 - zeta) (Eq. 13),
+ * zeta = t/b + 1 - t, and optionally alpha scaled with the sweep rate so that
+ * SR/alpha is fixed (Eq. 14 discussion).
+ *
+ * Conventions
+ *   - Every function returns an int status: SLLG_OK (0) or a negative
+ *     SLLG_E_* code; sllg_last_error() gives a thread-local message.
+ *   - Device memory is owned by the caller: one workspace of
+ *     sllg_workspace_bytes() bytes (256-byte aligned) passed to sllg_init().
+ *     The library never allocates or frees device memory.
+ *   - Work is enqueued on the caller's HIP stream (hipStream_t passed as
+ *     void*; NULL = the default stream).  sllg_run_* return without waiting;
+ *     sllg_loop, sllg_grad and sllg_get_state synchronise that stream.
+ *   - Host arrays are owned by the caller.  A context is not thread safe.
+ *   - SI units inside; fields in the loop outputs are in Oe.
+ */
+#ifndef SLLG_H
+#define SLLG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SLLG_OK = 0,
+    SLLG_E_INVAL = -1,      /* bad argument (dims, b < 1, dt <= 0, alpha < 0, T < 0, ...) */
+    SLLG_E_WORKSPACE = -2,  /* workspace missing, misaligned or too small                   */
+    SLLG_E_CAPACITY = -3,   /* host output array too small; *n_out holds the size needed     */
+    SLLG_E_STATE = -4,      /* call-order error (e.g. grad without checkpoints)              */
+    SLLG_E_HIP = -5,        /* HIP runtime error; text in sllg_last_error()                  */
+    SLLG_E_NUMERIC = -6     /* a cell's |m| became non-finite or drifted from 1              */
+};
+
+enum { SLLG_WAVE_TRIANGLE = 0, SLLG_WAVE_COSINE = 1, SLLG_WAVE_CONSTANT = 2 };
+
+/* Base (b = 1) material and field protocol.  Defaults quoted are the paper's. */
+typedef struct {
+    double a0_m;            /* cubic unit-cell edge, 0.839e-9 m                         */
+    double Ms0;             /* saturation magnetisation, 480e3 A/m                       */
+    double A0;              /* exchange stiffness, 0.98e-11 J/m                          */
+    double K0;              /* uniaxial anisotropy, 1e4 J/m^3                            */
+    double T_K;             /* temperature, 310 K                                        */
+    double Tc_K;            /* <= 0: 1.44 a0 A0/k_B; the paper prints 858 K              */
+    double delta;           /* Eq. (13) weight, 0.511                                    */
+    double easy_axis[3];    /* anisotropy axis (normalised by the library)               */
+    double Hmax_Oe;         /* physical field amplitude                                  */
+    double sweep_Oe_per_ns; /* SR; one cycle lasts 4 Hmax/SR                              */
+    int32_t wave;           /* SLLG_WAVE_*; both start at +Hmax                           */
+    int32_t n_cycles;       /* field cycles per sweep (>= 1)                              */
+    int32_t scale_AK;       /* apply A = zeta A0, K = zeta^3 K0                          */
+    int32_t scale_H;        /* apply H_sim = zeta H_phys and m_phys = (1-delta(1-zeta)) m */
+    double ms_scale;        /* Ms = ms_scale * Ms0 (not rescaled with b); 1 by default   */
+    double sr_ref_Oe_per_ns;/* > 0: alpha = alpha_ref * SR / SR_ref for every level      */
+    double alpha_ref;
+} sllg_material;
+
+/* One coarse-graining level: a grid and its realizations. */
+typedef struct {
+    int32_t nx, ny, nz;     /* cells; cell index i = x + nx*(y + ny*z)                    */
+    double b;               /* cell edge in units of a0 (>= 1)                            */
+    int32_t n_real;         /* independent realizations (>= 1)                            */
+    uint64_t seed_base;     /* realization r draws from seed_base + r                     */
+    double alpha;           /* Gilbert damping (ignored if sr_ref_Oe_per_ns > 0)          */
+    double dt_s;            /* time step; <= 0 picks the largest whole fs <= 5 fs within
+                               0.15 sqrt(1+alpha^2)/(gamma0 (12 c_ex + H_K + H_max))     */
+    double cone_deg;        /* > 0: per-cell easy axes uniform in a cone of this angle    */
+    uint64_t axis_seed;     /* Philox key for the per-cell axes                           */
+    int32_t record_every;   /* keep the loop ordinate every k steps (area and the online
+                               crossings still use every step); >= 1                      */
+} sllg_level;
+
+/* Loop statistics.  *_sim are in simulation units (Oe of the simulated field,
+ * unit-vector magnetisation); *_phys apply H/zeta and the Eq. (13) factor.
+ * Hc is half the distance between the first zero crossing on the falling
+ * branch and the first on the rising branch (linear interpolation); NaN when
+ * a branch never crosses zero.  S is -closed integral of m dH (trapezoid, every
+ * step).  S_se and Hc_se are one standard error over realizations (NaN for
+ * a single realization). */
+typedef struct {
+    double S_sim, S_phys;
+    double Hc_desc, Hc_asc;     /* crossing fields, Oe (sim)                      */
+    double Hc_sim, Hc_phys;
+    double Mr_sim, Mr_phys;     /* (m(H=0, falling) - m(H=0, rising))/2           */
+    double S_se, Hc_se;         /* standard errors of S_sim and Hc_sim            */
+    int32_t n_cross_desc, n_cross_asc; /* sign changes of m on each branch        */
+    int32_t n_real;             /* realizations the statistics cover              */
+} sllg_loop_stats;
+
+typedef struct sllg_ctx sllg_ctx;
+
+/* Bytes of device workspace a context needs.  ckpt_every > 0 reserves a
+ * checkpoint of every instance every ckpt_every steps (needed by sllg_grad). */
+size_t sllg_workspace_bytes(const sllg_material* mat, const sllg_level* levels,
+                            int32_t n_levels, int32_t ckpt_every);
+
+/* Compile every level's parameters (FP64 on the host: zeta, A, K, Ms, c_ex =
+ * 2A/(mu0 Ms a^2), H_K = 2K/(mu0 Ms), gamma1 = mu0 gamma_e/(1+alpha^2),
+ * sigma = sqrt(2 alpha k_B T/(gamma0 mu0 Ms V dt)), dt, steps per sweep),
+ * lay the state, loop records and checkpoints out in d_workspace, choose an
+ * execution plan for every level (tuned on first use of a shape) and set every
+ * cell to +z at step 0.  The workspace must stay valid until sllg_free(). */
+int sllg_init(const sllg_material* mat, const sllg_level* levels, int32_t n_levels,
+              int32_t ckpt_every, void* d_workspace, size_t ws_bytes,
+              void* hip_stream, sllg_ctx** out);
+
+/* Enqueue the remaining steps of the sweep for every level and realization. */
+int sllg_run_sweep(sllg_ctx* ctx);
+
+/* Enqueue at most nsteps further steps (levels stop at their own sweep end). */
+int sllg_run_steps(sllg_ctx* ctx, int64_t nsteps);
+
+/* Reset every level to step 0 (all cells +z, loops cleared). */
+int sllg_reset(sllg_ctx* ctx);
+
+/* Copy one loop to the host and analyse it.  real = -1 gives the ensemble
+ * mean loop (statistics of the mean loop, standard errors over realizations).
+ * H_Oe and mH (either may be NULL) receive the simulated field and loop
+ * ordinate at every recorded step, up to cap entries; *n_out gets the count.
+ * Synchronises the stream. */
+int sllg_loop(sllg_ctx* ctx, int32_t level, int32_t real, double* H_Oe, double* mH,
+              int64_t cap, int64_t* n_out, sllg_loop_stats* stats);
+
+/* Gradients, by the discrete adjoint of the Heun step under the same noise,
+ * of the ensemble-mean loop area S_sim (g_area) and of the coercive field
+ * Hc_sim of the ensemble-mean loop (g_hc) with respect to
+ * (K, A, alpha, ms_scale), K and A being the level's simulated values.
+ * Needs a completed sweep run with ckpt_every > 0 and record_every == 1.
+ * g_hc is NaN when the mean loop has no crossing on a branch.
+ * FP64 accumulation; synchronises the stream. */
+int sllg_grad(sllg_ctx* ctx, int32_t level, double g_area[4], double g_hc[4]);
+
+/* Thread-local text of the last error. */
+const char* sllg_last_error(void);
+
+/* Release the context (never the caller's workspace or stream). */
+void sllg_free(sllg_ctx* ctx);
+
+/* ---- introspection used by tests and the benchmark ---------------------- */
+
+/* Compiled constants of a level: out[0..15] = zeta, A, K, Ms, a, c_ex, hk,
+ * gamma1, alpha, sigma, dt, hscale, cM, n_steps, hz_amp (A/m), level plan id. */
+int sllg_level_params(const sllg_ctx* ctx, int32_t level, double out[16]);
+
+/* Current step index of a level. */
+int64_t sllg_level_step(const sllg_ctx* ctx, int32_t level);
+
+/* Copy one realization's magnetisation (host, 3*ncell floats, planes
+ * mx | my | mz) after synchronising the stream. */
+int sllg_get_state(sllg_ctx* ctx, int32_t level, int32_t real, float* host_m);
+
+/* Overwrite one realization's magnetisation from the host (3*ncell floats,
+ * planes mx | my | mz; vectors are used as given). */
+int sllg_set_state(sllg_ctx* ctx, int32_t level, int32_t real, const float* host_m);
+
+/* Execution plan of a level: 0 = automatic, 1 = LDS-resident persistent
+ * kernel, 2 = one fused launch per step over tiles.  Changing the plan is
+ * allowed between runs.  Returns SLLG_E_INVAL if the plan cannot hold the
+ * level. */
+int sllg_set_plan(sllg_ctx* ctx, int32_t level, int32_t plan);
+
+/* Device Philox4x32-10 of the thermal-noise stream: for k < n, the four raw
+ * words for (seed, level, tag, cells[k], steps[k]) and the three normals the
+ * kernels derive from them.  d_scratch: >= 40*n bytes of device memory.
+ * Synchronises the stream. */
+int sllg_philox_probe(uint64_t seed, uint32_t level, uint32_t tag, const uint32_t* cells,
+                      const uint64_t* steps, int32_t n, uint32_t* raw, float* normals,
+                      void* d_scratch, void* hip_stream);
+
+/* Per-cell easy axes of a level as the kernels use them (host, 3*ncell floats,
+ * planes ux | uy | uz).  Synchronises the stream. */
+int sllg_get_axes(sllg_ctx* ctx, int32_t level, float* host_u);
+
+/* Mean time of the dominant kernel's launches since the last call
+ * (milliseconds, from HIP events on the context stream) and the number of
+ * launches timed; timing is enabled by sllg_set_timing(ctx, 1). */
+int sllg_set_timing(sllg_ctx* ctx, int32_t on);
+int sllg_kernel_time(sllg_ctx* ctx, double* mean_ms, int64_t* launches, int64_t* cells_per_launch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SLLG_H */

@@ -1,0 +1,11 @@
+"""MI355X-native stochastic-LLG dynamic-hysteresis engine.
+
+The hot path (Heun integration of the stochastic Landau-Lifshitz-Gilbert
+equation on macrospin grids, with the loop reduced every step) runs in the
+gfx950 kernels of ``libsllg.so`` behind the C ABI of ``include/sllg.h``;
+``sllg`` is its Python binding.
+"""
+from .sllg import (PLAN_AUTO, PLAN_RESIDENT, PLAN_STREAM, Sim, SllgError,  # noqa: F401
+                   lib, philox_probe)
+
+__all__ = ["Sim", "SllgError", "lib", "philox_probe", "PLAN_AUTO", "PLAN_RESIDENT", "PLAN_STREAM"]

@@ -1,0 +1,221 @@
+// Per-cell device arithmetic of the stochastic LLG step for gfx950.
+//
+// Every kernel of the library calls these functions, so the FP32 arithmetic
+// of a cell is the same whichever execution plan runs it (the library is
+// built with -ffp-contract=off; fused multiply-adds are written out).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "sllg_types.hpp"
+
+namespace sllg {
+
+struct V3 {
+    float x, y, z;
+};
+
+__device__ __forceinline__ V3 v3(float x, float y, float z) { return V3{x, y, z}; }
+
+__device__ __forceinline__ V3 cross3(V3 a, V3 b)
+{
+    return V3{fmaf(a.y, b.z, -a.z * b.y), fmaf(a.z, b.x, -a.x * b.z), fmaf(a.x, b.y, -a.y * b.x)};
+}
+
+__device__ __forceinline__ float dot3(V3 a, V3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Counter words 0 and 2
+// are multiplied by the round multipliers; the new word 0 is hi(word2 product)
+// ^ word1 ^ key0, word 1 the low half of that product, word 2 hi(word0
+// product) ^ word3 ^ key1, word 3 its low half; the key then advances by the
+// Weyl constants.
+// ---------------------------------------------------------------------------
+struct U4 {
+    uint32_t a, b, c, d;
+};
+
+__device__ __forceinline__ U4 philox10(U4 w, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p = static_cast<uint64_t>(0xD2511F53u) * w.a;
+        const uint64_t s = static_cast<uint64_t>(0xCD9E8D57u) * w.c;
+        U4 n;
+        n.a = static_cast<uint32_t>(s >> 32) ^ w.b ^ k0;
+        n.b = static_cast<uint32_t>(s);
+        n.c = static_cast<uint32_t>(p >> 32) ^ w.d ^ k1;
+        n.d = static_cast<uint32_t>(p);
+        w = n;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return w;
+}
+
+// Raw words for (seed, level tag, purpose tag, cell, step).
+__device__ __forceinline__ U4 philox_cell(uint64_t seed, uint32_t level, uint32_t tag,
+                                          uint32_t cell, uint64_t step)
+{
+    U4 ctr;
+    ctr.a = cell;
+    ctr.b = static_cast<uint32_t>(step);
+    ctr.c = (static_cast<uint32_t>(step >> 32) & 0xFFFFu) | ((level & 0xFFu) << 16) | (tag << 24);
+    ctr.d = 0u;
+    return philox10(ctr, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
+}
+
+// 23 random bits with a half-step offset: (2k+1)/2^24, exact in FP32.
+__device__ __forceinline__ float unit_open(uint32_t w)
+{
+    return static_cast<float>(((w >> 9) << 1) | 1u) * 5.9604644775390625e-8f;
+}
+
+// Box-Muller with the hardware transcendentals: v_log_f32 is log2, v_sin_f32
+// and v_cos_f32 take the angle in revolutions (so 2*pi*u needs no reduction).
+__device__ __forceinline__ V3 gauss3(U4 w)
+{
+    const float u0 = unit_open(w.a), u1 = unit_open(w.b);
+    const float u2 = unit_open(w.c), u3 = unit_open(w.d);
+    const float kMinus2Ln2 = -1.3862943611198906f;  // -2 ln 2
+    const float r0 = __builtin_amdgcn_sqrtf(kMinus2Ln2 * __builtin_amdgcn_logf(u0));
+    const float r2 = __builtin_amdgcn_sqrtf(kMinus2Ln2 * __builtin_amdgcn_logf(u2));
+    return V3{r0 * __builtin_amdgcn_cosf(u1), r0 * __builtin_amdgcn_sinf(u1),
+              r2 * __builtin_amdgcn_cosf(u3)};
+}
+
+// ---------------------------------------------------------------------------
+// Field protocol
+// ---------------------------------------------------------------------------
+// Fraction of the peak applied field at step n (FP64).
+__device__ __forceinline__ double wave_at(const LevelDev& L, int64_t n)
+{
+    const int64_t N = L.n_period;
+    const int64_t k = n % N;
+    if (L.wave == 0) {
+        const double s = static_cast<double>(k) / static_cast<double>(N);
+        return (2 * k <= N) ? 1.0 - 4.0 * s : 4.0 * s - 3.0;
+    }
+    if (L.wave == 1) {
+        return cospi(2.0 * static_cast<double>(k) / static_cast<double>(N));
+    }
+    return 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// Effective field and the Landau-Lifshitz right-hand side (Eq. 1 / Ms):
+//   H = c_ex * sum_j (m_j - m_i) + H_K (m.u) u + hz z + H_th
+//   f = -gamma1 m x H - alpha gamma1 m x (m x H)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ V3 eff_field(float c_ex, float hk, V3 m, V3 ex, V3 u, float hz, V3 hth)
+{
+    const float a = hk * dot3(m, u);
+    V3 H;
+    H.x = fmaf(c_ex, ex.x, fmaf(a, u.x, hth.x));
+    H.y = fmaf(c_ex, ex.y, fmaf(a, u.y, hth.y));
+    H.z = fmaf(c_ex, ex.z, fmaf(a, u.z, hth.z + hz));
+    return H;
+}
+
+__device__ __forceinline__ V3 llg_rhs(float g1, float ag1, V3 m, V3 H)
+{
+    const V3 t = cross3(m, H);
+    const V3 d = cross3(m, t);
+    return V3{-fmaf(g1, t.x, ag1 * d.x), -fmaf(g1, t.y, ag1 * d.y), -fmaf(g1, t.z, ag1 * d.z)};
+}
+
+__device__ __forceinline__ V3 normalized(V3 p)
+{
+    const float r = __builtin_amdgcn_rsqf(dot3(p, p));
+    return V3{p.x * r, p.y * r, p.z * r};
+}
+
+// Sum over the six face neighbours of (m_j - m_i); a missing neighbour is
+// passed as the cell itself and contributes exactly zero.
+__device__ __forceinline__ V3 nb_sum(V3 m, V3 xm, V3 xp, V3 ym, V3 yp, V3 zm, V3 zp)
+{
+    V3 e;
+    e.x = (((((xm.x - m.x) + (xp.x - m.x)) + (ym.x - m.x)) + (yp.x - m.x)) + (zm.x - m.x)) + (zp.x - m.x);
+    e.y = (((((xm.y - m.y) + (xp.y - m.y)) + (ym.y - m.y)) + (yp.y - m.y)) + (zm.y - m.y)) + (zp.y - m.y);
+    e.z = (((((xm.z - m.z) + (xp.z - m.z)) + (ym.z - m.z)) + (yp.z - m.z)) + (zm.z - m.z)) + (zp.z - m.z);
+    return e;
+}
+
+// Predictor stage: m' = (m + dt f)/|.|; also q = m + dt/2 f for the corrector.
+__device__ __forceinline__ void heun_predict(const LevelDev& L, V3 m, V3 ex, V3 u, float hz, V3 hth,
+                                             V3& mp, V3& q)
+{
+    const V3 H = eff_field(L.c_ex, L.hk, m, ex, u, hz, hth);
+    const V3 f = llg_rhs(L.g1, L.ag1, m, H);
+    mp = normalized(V3{fmaf(L.dt, f.x, m.x), fmaf(L.dt, f.y, m.y), fmaf(L.dt, f.z, m.z)});
+    q = V3{fmaf(L.half_dt, f.x, m.x), fmaf(L.half_dt, f.y, m.y), fmaf(L.half_dt, f.z, m.z)};
+}
+
+// Corrector stage: m_{n+1} = (q + dt/2 f(m', H'))/|.|.
+__device__ __forceinline__ V3 heun_correct(const LevelDev& L, V3 mp, V3 exp_, V3 u, float hz1, V3 hth,
+                                           V3 q)
+{
+    const V3 H = eff_field(L.c_ex, L.hk, mp, exp_, u, hz1, hth);
+    const V3 f = llg_rhs(L.g1, L.ag1, mp, H);
+    return normalized(V3{fmaf(L.half_dt, f.x, q.x), fmaf(L.half_dt, f.y, q.y), fmaf(L.half_dt, f.z, q.z)});
+}
+
+__device__ __forceinline__ V3 thermal_field(const LevelDev& L, uint64_t seed, uint32_t cell, int64_t n)
+{
+    const V3 xi = gauss3(philox_cell(seed, static_cast<uint32_t>(L.level_tag), kTagNoise, cell,
+                                     static_cast<uint64_t>(n)));
+    return V3{L.sigma * xi.x, L.sigma * xi.y, L.sigma * xi.z};
+}
+
+// ---------------------------------------------------------------------------
+// Online loop accumulation for one instance at step n -> n+1 (FP64).
+// ---------------------------------------------------------------------------
+__device__ inline void loop_accumulate(AccDev& a, const LevelDev& L, int64_t n, double m_new,
+                                       double* rec)
+{
+    const double h0 = L.hz_oe * wave_at(L, n);
+    const double h1 = L.hz_oe * wave_at(L, n + 1);
+    const double dH = h1 - h0;
+    const double m0 = a.m_prev;
+    a.area -= 0.5 * (m0 + m_new) * dH;
+    const int change = (m0 > 0.0) != (m_new > 0.0);
+    if (dH < 0.0) {
+        a.ncross_d += change;
+        if (!a.found_d && m0 > 0.0 && m_new <= 0.0) {
+            a.found_d = 1;
+            a.hstar_d = h0 - m0 * dH / (m_new - m0);
+        }
+        if (!a.found0_d && h0 > 0.0 && h1 <= 0.0) {
+            a.found0_d = 1;
+            a.m0_d = m0 + (m_new - m0) * (0.0 - h0) / dH;
+        }
+    } else if (dH > 0.0) {
+        a.ncross_a += change;
+        if (!a.found_a && m0 < 0.0 && m_new >= 0.0) {
+            a.found_a = 1;
+            a.hstar_a = h0 - m0 * dH / (m_new - m0);
+        }
+        if (!a.found0_a && h0 < 0.0 && h1 >= 0.0) {
+            a.found0_a = 1;
+            a.m0_a = m0 + (m_new - m0) * (0.0 - h0) / dH;
+        }
+    }
+    a.m_prev = m_new;
+    if ((n + 1) % L.record_every == 0) rec[(n + 1) / L.record_every] = m_new;
+}
+
+// Wave-wide FP32 sum (all 64 lanes end with the total).
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+}  // namespace sllg

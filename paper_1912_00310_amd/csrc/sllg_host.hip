@@ -1,0 +1,1234 @@
+// Host runtime and C ABI of the stochastic-LLG hysteresis-loop library.
+//
+//   - parameter compiler: the modified Grinstein-Koch rule per level (FP64)
+//   - workspace layout: every device buffer carved from the caller's block
+//   - planner: LDS-resident groups or streamed tiles per level, with a small
+//     timing-based tuner for the tile shape
+//   - launch sequencing on the caller's stream, optional HIP graphs
+//   - loop analytics (FP64) and the adjoint driver
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/sllg.h"
+#include "sllg_types.hpp"
+
+// The kernels are compiled in this translation unit (one shared library).
+#include "sllg_kernels.hip"
+
+using namespace sllg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_OK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(SLLG_E_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                        __LINE__);                                                          \
+    } while (0)
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kMu0 = 4.0e-7 * kPi;
+constexpr double kKB = 1.380649e-23;
+constexpr double kGammaE = 1.76e11;
+constexpr double kGamma0 = kMu0 * kGammaE;
+constexpr double kOe = 1000.0 / (4.0 * kPi);   // A/m per Oe
+
+constexpr int kPlanAuto = 0, kPlanResident = 1, kPlanStream = 2;
+
+// Compiled FP64 constants of one level.
+struct LevelHost {
+    sllg_level in;
+    double t, zeta, A, K, Ms, a, V, alpha, dt, c_ex, hk, gamma1, sigma, hscale, cM, hz_amp;
+    int64_t n_period, n_steps, n_rec;
+    int inst0, ninst;
+    int64_t ncell;
+    int64_t axes_off;     // float offset in the axes buffer (-1: uniform axis)
+    int plan;             // kPlanResident / kPlanStream in use
+    int forced;           // plan fixed by sllg_set_plan
+    // stream plan
+    int shape;            // index into kShapes
+    int tz;
+    int tile0, ntiles;
+    int64_t step;         // host view of the step index
+};
+
+struct Shape {
+    int tx, ty, pz;
+};
+// tile shapes the stream kernel is instantiated for
+const Shape kShapes[] = {{64, 8, 1}, {32, 16, 1}, {64, 16, 1}, {32, 8, 2}, {8, 24, 4},
+                         {8, 24, 2}, {8, 24, 1}, {16, 16, 2}, {4, 12, 8}};
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+const int kTzChoices[] = {1, 2, 4, 8, 16, 32, 64};
+
+struct ResidentKernel {
+    int nw, cpw;
+};
+const ResidentKernel kResKernels[] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {16, 1}, {16, 2}, {16, 4}, {8, 8}};
+
+// Layout of the workspace (byte offsets).
+struct Layout {
+    size_t levels, insts, accs, steps, status, inst_cnt, launch_cnt, partials, tiles, groups, slots,
+        chunks, buf0, buf1, axes, records, ckpt, tape, lam, weights, grads, total;
+    int64_t state_floats, axes_floats, rec_doubles, ckpt_floats, tape_floats, lam_floats,
+        max_tiles, max_groups, max_chunks, max_w, ninst_total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+int64_t tiles_for(const sllg_level& L, const Shape& s, int tz)
+{
+    return ceil_div(L.nx, s.tx) * ceil_div(L.ny, s.ty) * ceil_div(L.nz, tz);
+}
+
+int64_t max_tiles_for(const sllg_level& L)
+{
+    int64_t m = 0;
+    for (const Shape& s : kShapes)
+        for (int tz : kTzChoices) m = std::max(m, tiles_for(L, s, tz));
+    return m;
+}
+
+}  // namespace
+
+struct sllg_ctx {
+    sllg_material mat{};
+    std::vector<LevelHost> lv;
+    int ckpt_every = 0;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    Layout lay{};
+    // device views
+    LevelDev* d_levels = nullptr;
+    InstDev* d_insts = nullptr;
+    AccDev* d_accs = nullptr;
+    int64_t* d_steps = nullptr;
+    int* d_status = nullptr;
+    uint32_t* d_inst_cnt = nullptr;
+    uint32_t* d_launch_cnt = nullptr;
+    double* d_partials = nullptr;
+    TileDev* d_tiles = nullptr;
+    GroupDev* d_groups = nullptr;
+    SlotDev* d_slots = nullptr;
+    ChunkDev* d_chunks = nullptr;
+    float* d_buf0 = nullptr;
+    float* d_buf1 = nullptr;
+    float* d_axes = nullptr;
+    double* d_records = nullptr;
+    float* d_ckpt = nullptr;
+    float* d_tape = nullptr;
+    float* d_lam = nullptr;
+    double* d_weights = nullptr;
+    double* d_grads = nullptr;
+    // host mirrors
+    std::vector<LevelDev> h_levels;
+    std::vector<InstDev> h_insts;
+    std::vector<TileDev> h_tiles;
+    // resident sets: levels advanced together by one launch sequence
+    struct ResSet {
+        std::vector<int> levels;
+        int group0 = 0, ngroups = 0;
+        int nw = 1, cpw = 1;
+        size_t lds = 0;
+    };
+    std::vector<ResSet> res_sets;
+    std::vector<GroupDev> h_groups;
+    std::vector<SlotDev> h_slots;
+    std::vector<ChunkDev> h_chunks;
+    // timing of the dominant kernel
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    int64_t timed_cells = 0;
+    int max_lds = 65536;
+    int num_cus = 256;
+    bool use_graph = false;
+    std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Parameter compiler (modified Grinstein-Koch rule).
+// ---------------------------------------------------------------------------
+int validate(const sllg_material* m, const sllg_level* L, int n)
+{
+    if (!m || !L || n < 1 || n > 255) return fail(SLLG_E_INVAL, "need 1..255 levels and a material");
+    if (!(m->a0_m > 0) || !(m->Ms0 > 0) || !(m->A0 >= 0) || !(m->K0 >= 0) || !(m->T_K >= 0))
+        return fail(SLLG_E_INVAL, "material: a0, Ms0 > 0; A0, K0, T >= 0 required");
+    if (!(m->Hmax_Oe >= 0) || !(m->sweep_Oe_per_ns > 0) || m->n_cycles < 1)
+        return fail(SLLG_E_INVAL, "protocol: Hmax >= 0, sweep rate > 0, n_cycles >= 1 required");
+    if (m->wave < 0 || m->wave > 2) return fail(SLLG_E_INVAL, "unknown waveform %d", m->wave);
+    double an = std::sqrt(m->easy_axis[0] * m->easy_axis[0] + m->easy_axis[1] * m->easy_axis[1] +
+                          m->easy_axis[2] * m->easy_axis[2]);
+    if (!(an > 0) || !std::isfinite(an)) return fail(SLLG_E_INVAL, "easy axis must be non-zero");
+    if (!(m->ms_scale > 0)) return fail(SLLG_E_INVAL, "ms_scale must be > 0");
+    if (m->sr_ref_Oe_per_ns > 0 && !(m->alpha_ref >= 0))
+        return fail(SLLG_E_INVAL, "alpha_ref must be >= 0");
+    for (int i = 0; i < n; ++i) {
+        const sllg_level& l = L[i];
+        if (l.nx < 1 || l.ny < 1 || l.nz < 1 || l.nx > 1023 || l.ny > 1023 || l.nz > 1023 ||
+            (int64_t)l.nx * l.ny * l.nz > (1 << 26))
+            return fail(SLLG_E_INVAL, "level %d: dims must be 1..1023 and at most 2^26 cells", i);
+        if (!(l.b >= 1.0)) return fail(SLLG_E_INVAL, "level %d: b must be >= 1", i);
+        if (l.n_real < 1) return fail(SLLG_E_INVAL, "level %d: n_real must be >= 1", i);
+        if (!(l.alpha >= 0) && !(m->sr_ref_Oe_per_ns > 0))
+            return fail(SLLG_E_INVAL, "level %d: alpha must be >= 0", i);
+        if (l.dt_s < 0 || !std::isfinite(l.dt_s)) return fail(SLLG_E_INVAL, "level %d: dt must be >= 0", i);
+        if (!(l.cone_deg >= 0) || l.cone_deg >= 90) return fail(SLLG_E_INVAL, "level %d: cone in [0, 90)", i);
+        if (l.record_every < 1) return fail(SLLG_E_INVAL, "level %d: record_every must be >= 1", i);
+    }
+    return SLLG_OK;
+}
+
+void compile_level(const sllg_material& m, const sllg_level& in, LevelHost& o)
+{
+    o.in = in;
+    const double Tc = m.Tc_K > 0 ? m.Tc_K : 1.44 * m.a0_m * m.A0 / kKB;
+    o.t = m.T_K / Tc;
+    o.zeta = o.t / in.b + 1.0 - o.t;                      // text after Eq. (11)
+    o.A = m.scale_AK ? o.zeta * m.A0 : m.A0;              // Eq. (8)
+    o.K = m.scale_AK ? o.zeta * o.zeta * o.zeta * m.K0 : m.K0;   // Eq. (9)
+    o.hscale = m.scale_H ? o.zeta : 1.0;                  // Eq. (10)
+    o.cM = m.scale_H ? 1.0 - m.delta * (1.0 - o.zeta) : 1.0;     // Eq. (13)
+    o.Ms = m.ms_scale * m.Ms0;
+    o.a = in.b * m.a0_m;
+    o.V = o.a * o.a * o.a;
+    o.alpha = m.sr_ref_Oe_per_ns > 0 ? m.alpha_ref * m.sweep_Oe_per_ns / m.sr_ref_Oe_per_ns : in.alpha;
+    o.c_ex = 2.0 * o.A / (kMu0 * o.Ms * o.a * o.a);
+    o.hk = 2.0 * o.K / (kMu0 * o.Ms);
+    o.hz_amp = o.hscale * m.Hmax_Oe * kOe;
+    if (in.dt_s > 0) {
+        o.dt = in.dt_s;
+    } else {
+        const double bound = 0.15 * std::sqrt(1.0 + o.alpha * o.alpha) /
+                             (kGamma0 * (12.0 * o.c_ex + o.hk + o.hz_amp));
+        double fs = std::floor(bound / 1e-15);
+        fs = std::max(1.0, std::min(5.0, fs));
+        o.dt = fs * 1e-15;
+    }
+    o.gamma1 = kGamma0 / (1.0 + o.alpha * o.alpha);
+    o.sigma = std::sqrt(2.0 * o.alpha * kKB * m.T_K / (kGamma0 * kMu0 * o.Ms * o.V * o.dt));
+    const double period = 4.0 * m.Hmax_Oe / (m.sweep_Oe_per_ns * 1e9);
+    o.n_period = std::max<int64_t>(1, (int64_t)std::llround(period / o.dt));
+    o.n_steps = o.n_period * m.n_cycles;
+    o.n_rec = o.n_steps / in.record_every + 1;
+    o.ncell = (int64_t)in.nx * in.ny * in.nz;
+}
+
+LevelDev to_dev(const sllg_material& m, const LevelHost& h, int tag)
+{
+    LevelDev d{};
+    d.c_ex = (float)h.c_ex;
+    d.hk = (float)h.hk;
+    d.g1 = (float)h.gamma1;
+    d.ag1 = (float)(h.alpha * h.gamma1);
+    d.sigma = (float)h.sigma;
+    d.dt = (float)h.dt;
+    d.half_dt = (float)(0.5 * h.dt);
+    const double an = std::sqrt(m.easy_axis[0] * m.easy_axis[0] + m.easy_axis[1] * m.easy_axis[1] +
+                                m.easy_axis[2] * m.easy_axis[2]);
+    d.ux = (float)(m.easy_axis[0] / an);
+    d.uy = (float)(m.easy_axis[1] / an);
+    d.uz = (float)(m.easy_axis[2] / an);
+    d.hz_amp = h.hz_amp;
+    d.hz_oe = h.hz_amp / kOe;
+    d.n_period = h.n_period;
+    d.n_steps = h.n_steps;
+    d.wave = m.wave;
+    d.level_tag = tag;
+    d.record_every = h.in.record_every;
+    d.ncell = (int32_t)h.ncell;
+    d.nx = h.in.nx;
+    d.ny = h.in.ny;
+    d.nz = h.in.nz;
+    d.has_axes = h.axes_off >= 0 ? 1 : 0;
+    d.axes_off = h.axes_off >= 0 ? h.axes_off : 0;
+    d.n_rec = h.n_rec;
+    return d;
+}
+
+int resident_fits(const LevelHost& h, int max_lds)
+{
+    // two AoS copies of the state plus per-chunk and per-slot bookkeeping
+    const int64_t chunks = ceil_div(h.ncell, 64);
+    const int64_t bytes = 24 * h.ncell + 4 * chunks + 64 + (int64_t)sizeof(AccDev);
+    return bytes <= max_lds && chunks <= 64;
+}
+
+Layout make_layout(const sllg_material& m, const std::vector<LevelHost>& lv, int ckpt_every)
+{
+    Layout L{};
+    int64_t ninst = 0, state = 0, axes = 0, rec = 0, ckpt = 0, tiles = 0, chunks = 0, tape = 0, lam = 0,
+            maxw = 0;
+    for (const LevelHost& h : lv) {
+        ninst += h.in.n_real;
+        state += 3 * h.ncell * h.in.n_real;
+        if (h.in.cone_deg > 0) axes += 3 * h.ncell;
+        rec += h.n_rec * h.in.n_real;
+        if (ckpt_every > 0) {
+            const int64_t nck = ceil_div(h.n_steps, ckpt_every);
+            ckpt += nck * 3 * h.ncell * h.in.n_real;
+            tape = std::max<int64_t>(tape, (int64_t)ckpt_every * 9 * h.ncell * h.in.n_real);
+            lam = std::max<int64_t>(lam, 6 * h.ncell * h.in.n_real);
+            maxw = std::max<int64_t>(maxw, h.n_steps + 1);
+        }
+        tiles += max_tiles_for(h.in) * h.in.n_real;
+        chunks += ceil_div(h.ncell, 64) * h.in.n_real;
+    }
+    (void)m;
+    L.ninst_total = ninst;
+    L.state_floats = state;
+    L.axes_floats = axes;
+    L.rec_doubles = rec;
+    L.ckpt_floats = ckpt;
+    L.tape_floats = tape;
+    L.lam_floats = lam;
+    L.max_tiles = tiles;
+    L.max_chunks = chunks;
+    L.max_groups = ninst;
+    L.max_w = maxw;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + std::max<size_t>(bytes, 1));
+        return at;
+    };
+    L.levels = take(sizeof(LevelDev) * lv.size());
+    L.insts = take(sizeof(InstDev) * ninst);
+    L.accs = take(sizeof(AccDev) * ninst);
+    L.steps = take(sizeof(int64_t) * lv.size());
+    L.status = take(sizeof(int) * 4);
+    L.inst_cnt = take(sizeof(uint32_t) * ninst);
+    L.launch_cnt = take(sizeof(uint32_t) * (lv.size() + 1));
+    L.partials = take(sizeof(double) * tiles);
+    L.tiles = take(sizeof(TileDev) * tiles);
+    L.groups = take(sizeof(GroupDev) * ninst);
+    L.slots = take(sizeof(SlotDev) * ninst);
+    L.chunks = take(sizeof(ChunkDev) * chunks);
+    L.buf0 = take(sizeof(float) * state);
+    L.buf1 = take(sizeof(float) * state);
+    L.axes = take(sizeof(float) * axes);
+    L.records = take(sizeof(double) * rec);
+    L.ckpt = take(sizeof(float) * ckpt);
+    L.tape = take(sizeof(float) * tape);
+    L.lam = take(sizeof(float) * lam);
+    L.weights = take(sizeof(double) * 2 * maxw);
+    L.grads = take(sizeof(double) * 10 * ninst);
+    L.total = o;
+    return L;
+}
+
+// ---------------------------------------------------------------------------
+// Planning
+// ---------------------------------------------------------------------------
+void build_tiles(sllg_ctx* C, LevelHost& h)
+{
+    const Shape s = kShapes[h.shape];
+    h.tile0 = (int)C->h_tiles.size();
+    for (int r = 0; r < h.ninst; ++r) {
+        InstDev& I = C->h_insts[h.inst0 + r];
+        I.tile0 = (int)C->h_tiles.size();
+        for (int z0 = 0; z0 < h.in.nz; z0 += h.tz)
+            for (int y0 = 0; y0 < h.in.ny; y0 += s.ty)
+                for (int x0 = 0; x0 < h.in.nx; x0 += s.tx) {
+                    TileDev t{};
+                    t.inst = h.inst0 + r;
+                    t.x0 = (int16_t)x0;
+                    t.y0 = (int16_t)y0;
+                    t.z0 = (int16_t)z0;
+                    t.nxt = (int16_t)std::min(s.tx, h.in.nx - x0);
+                    t.nyt = (int16_t)std::min(s.ty, h.in.ny - y0);
+                    t.nzt = (int16_t)std::min(h.tz, h.in.nz - z0);
+                    C->h_tiles.push_back(t);
+                }
+        I.ntiles = (int)C->h_tiles.size() - I.tile0;
+    }
+    h.ntiles = (int)C->h_tiles.size() - h.tile0;
+}
+
+// Default stream shape: whole x-y planes when they fit a shape, else the
+// widest x tile; z ranges long enough to amortise the two halo planes while
+// keeping several workgroups per compute unit.
+void default_stream_shape(const sllg_ctx* C, LevelHost& h)
+{
+    int best = -1;
+    for (int i = 0; i < kNumShapes; ++i)
+        if (kShapes[i].tx >= h.in.nx && kShapes[i].ty >= h.in.ny) {
+            if (best < 0 || kShapes[i].tx * kShapes[i].ty < kShapes[best].tx * kShapes[best].ty ||
+                (kShapes[i].tx * kShapes[i].ty == kShapes[best].tx * kShapes[best].ty &&
+                 kShapes[i].pz > kShapes[best].pz))
+                best = i;
+        }
+    if (best < 0) best = 0;
+    h.shape = best;
+    const Shape s = kShapes[best];
+    const int64_t xy = ceil_div(h.in.nx, s.tx) * ceil_div(h.in.ny, s.ty) * h.ninst;
+    int tz = 64;
+    while (tz > 1 && xy * ceil_div(h.in.nz, tz) < 4LL * C->num_cus) tz /= 2;
+    h.tz = std::max(tz, s.pz > 1 ? std::min(s.pz, h.in.nz) : 1);
+}
+
+// Group instances of resident levels with equal sweep length.
+int build_resident(sllg_ctx* C)
+{
+    C->res_sets.clear();
+    C->h_groups.clear();
+    C->h_slots.clear();
+    C->h_chunks.clear();
+    std::map<int64_t, std::vector<int>> by_len;
+    for (int l = 0; l < (int)C->lv.size(); ++l)
+        if (C->lv[l].plan == kPlanResident) by_len[C->lv[l].n_steps * 1000003 + C->lv[l].step].push_back(l);
+    for (auto& kv : by_len) {
+        sllg_ctx::ResSet rs;
+        rs.levels = kv.second;
+        // instances, largest first
+        std::vector<int> inst;
+        int64_t total = 0;
+        for (int l : rs.levels)
+            for (int r = 0; r < C->lv[l].ninst; ++r) {
+                inst.push_back(C->lv[l].inst0 + r);
+                total++;
+            }
+        std::stable_sort(inst.begin(), inst.end(), [&](int a, int b) {
+            return C->lv[C->h_insts[a].level].ncell > C->lv[C->h_insts[b].level].ncell;
+        });
+        // number of groups: one instance per group up to two per CU, else pack
+        int ng = (int)std::min<int64_t>(total, 2LL * C->num_cus);
+        if (total > 2LL * C->num_cus) ng = C->num_cus;
+        std::vector<std::vector<int>> members(ng);
+        std::vector<int64_t> load(ng, 0), lds(ng, 0);
+        for (size_t k = 0; k < inst.size(); ++k) {
+            // round-robin over the groups (instances sorted by size)
+            int g = (int)(k % ng);
+            const LevelHost& h = C->lv[C->h_insts[inst[k]].level];
+            members[g].push_back(inst[k]);
+            load[g] += ceil_div(h.ncell, 64);
+            lds[g] += 24 * h.ncell;
+        }
+        int64_t max_chunks = 0, max_lds = 0;
+        for (int g = 0; g < ng; ++g) {
+            max_chunks = std::max(max_chunks, load[g]);
+            max_lds = std::max<int64_t>(max_lds, lds[g] + 4 * load[g] + 32 +
+                                                     (int64_t)sizeof(AccDev) * members[g].size());
+        }
+        if (max_lds > C->max_lds)
+            return fail(SLLG_E_INVAL, "resident plan: %lld bytes of LDS per workgroup exceed %d",
+                        (long long)max_lds, C->max_lds);
+        int pick = -1;
+        for (int i = 0; i < (int)(sizeof(kResKernels) / sizeof(kResKernels[0])); ++i)
+            if (kResKernels[i].nw * kResKernels[i].cpw >= max_chunks) {
+                pick = i;
+                break;
+            }
+        if (pick < 0) return fail(SLLG_E_INVAL, "resident plan: %lld chunks per workgroup", (long long)max_chunks);
+        rs.nw = kResKernels[pick].nw;
+        rs.cpw = kResKernels[pick].cpw;
+        rs.group0 = (int)C->h_groups.size();
+        rs.ngroups = ng;
+        for (int g = 0; g < ng; ++g) {
+            GroupDev G{};
+            G.slot0 = (int)C->h_slots.size();
+            G.chunk0 = (int)C->h_chunks.size();
+            int cells = 0, nch = 0;
+            for (size_t s = 0; s < members[g].size(); ++s) {
+                const int ii = members[g][s];
+                const LevelHost& h = C->lv[C->h_insts[ii].level];
+                SlotDev S{};
+                S.inst = ii;
+                S.lds_off = cells;
+                S.chunk0 = nch;
+                S.nchunks = (int)ceil_div(h.ncell, 64);
+                for (int k = 0; k < S.nchunks; ++k) {
+                    ChunkDev ch{};
+                    ch.inst = ii;
+                    ch.slot = (int)s;
+                    ch.c0 = 64 * k;
+                    C->h_chunks.push_back(ch);
+                }
+                cells += (int)h.ncell;
+                nch += S.nchunks;
+                C->h_slots.push_back(S);
+            }
+            G.nslots = (int)members[g].size();
+            G.nchunks = nch;
+            G.ncells = cells;
+            C->h_groups.push_back(G);
+        }
+        rs.lds = (size_t)max_lds + 64;
+        C->res_sets.push_back(rs);
+    }
+    return SLLG_OK;
+}
+
+int upload_tables(sllg_ctx* C)
+{
+    if ((int64_t)C->h_tiles.size() > C->lay.max_tiles ||
+        (int64_t)C->h_chunks.size() > C->lay.max_chunks ||
+        (int64_t)C->h_groups.size() > C->lay.max_groups)
+        return fail(SLLG_E_WORKSPACE, "plan tables exceed the reserved workspace");
+    for (size_t l = 0; l < C->lv.size(); ++l) C->h_levels[l] = to_dev(C->mat, C->lv[l], (int)l);
+    HIP_OK(hipMemcpyAsync(C->d_levels, C->h_levels.data(), sizeof(LevelDev) * C->h_levels.size(),
+                          hipMemcpyHostToDevice, C->stream));
+    HIP_OK(hipMemcpyAsync(C->d_insts, C->h_insts.data(), sizeof(InstDev) * C->h_insts.size(),
+                          hipMemcpyHostToDevice, C->stream));
+    if (!C->h_tiles.empty())
+        HIP_OK(hipMemcpyAsync(C->d_tiles, C->h_tiles.data(), sizeof(TileDev) * C->h_tiles.size(),
+                              hipMemcpyHostToDevice, C->stream));
+    if (!C->h_groups.empty()) {
+        HIP_OK(hipMemcpyAsync(C->d_groups, C->h_groups.data(), sizeof(GroupDev) * C->h_groups.size(),
+                              hipMemcpyHostToDevice, C->stream));
+        HIP_OK(hipMemcpyAsync(C->d_slots, C->h_slots.data(), sizeof(SlotDev) * C->h_slots.size(),
+                              hipMemcpyHostToDevice, C->stream));
+        HIP_OK(hipMemcpyAsync(C->d_chunks, C->h_chunks.data(), sizeof(ChunkDev) * C->h_chunks.size(),
+                              hipMemcpyHostToDevice, C->stream));
+    }
+    HIP_OK(hipStreamSynchronize(C->stream));
+    return SLLG_OK;
+}
+
+int replan(sllg_ctx* C)
+{
+    C->h_tiles.clear();
+    for (LevelHost& h : C->lv)
+        if (h.plan == kPlanStream) build_tiles(C, h);
+    int rc = build_resident(C);
+    if (rc) return rc;
+    for (const auto& g : C->graphs) (void)hipGraphExecDestroy(g.second);
+    C->graphs.clear();
+    return upload_tables(C);
+}
+
+// ---------------------------------------------------------------------------
+// Launching
+// ---------------------------------------------------------------------------
+template <int NW, int CPW>
+hipError_t launch_res(sllg_ctx* C, const sllg_ctx::ResSet& rs, int64_t n0, int64_t ns)
+{
+    const size_t lds = rs.lds;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_resident<NW, CPW>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_resident<NW, CPW>), dim3(rs.ngroups), dim3(NW * 64), lds, C->stream,
+                       C->d_groups + rs.group0, C->d_slots, C->d_chunks, C->d_insts, C->d_levels,
+                       C->d_buf0, C->d_buf1, C->d_axes, C->d_records, C->d_accs, C->d_ckpt,
+                       C->ckpt_every, n0, ns, C->d_status);
+    return hipGetLastError();
+}
+
+hipError_t dispatch_res(sllg_ctx* C, const sllg_ctx::ResSet& rs, int64_t n0, int64_t ns)
+{
+    switch (rs.nw * 100 + rs.cpw) {
+    case 101: return launch_res<1, 1>(C, rs, n0, ns);
+    case 201: return launch_res<2, 1>(C, rs, n0, ns);
+    case 401: return launch_res<4, 1>(C, rs, n0, ns);
+    case 801: return launch_res<8, 1>(C, rs, n0, ns);
+    case 1601: return launch_res<16, 1>(C, rs, n0, ns);
+    case 1602: return launch_res<16, 2>(C, rs, n0, ns);
+    case 1604: return launch_res<16, 4>(C, rs, n0, ns);
+    case 808: return launch_res<8, 8>(C, rs, n0, ns);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int TX, int TY, int PZ>
+hipError_t launch_stream_t(sllg_ctx* C, int level)
+{
+    const LevelHost& h = C->lv[level];
+    hipLaunchKernelGGL((k_stream<TX, TY, PZ>), dim3(h.ntiles), dim3(TX * TY * PZ), 0, C->stream,
+                       C->d_tiles, C->d_insts, C->d_levels, C->d_buf0, C->d_buf1, C->d_axes,
+                       C->d_steps, level, 1, h.tile0, C->d_partials, C->d_inst_cnt,
+                       C->d_launch_cnt + level, C->d_records, C->d_accs, C->d_ckpt, C->ckpt_every,
+                       C->d_status);
+    return hipGetLastError();
+}
+
+hipError_t dispatch_stream(sllg_ctx* C, int level)
+{
+    const Shape s = kShapes[C->lv[level].shape];
+    const int key = s.tx * 10000 + s.ty * 10 + s.pz;
+    switch (key) {
+    case 640081: return launch_stream_t<64, 8, 1>(C, level);
+    case 320161: return launch_stream_t<32, 16, 1>(C, level);
+    case 640161: return launch_stream_t<64, 16, 1>(C, level);
+    case 320082: return launch_stream_t<32, 8, 2>(C, level);
+    case 80244: return launch_stream_t<8, 24, 4>(C, level);
+    case 80242: return launch_stream_t<8, 24, 2>(C, level);
+    case 80241: return launch_stream_t<8, 24, 1>(C, level);
+    case 160162: return launch_stream_t<16, 16, 2>(C, level);
+    case 40128: return launch_stream_t<4, 12, 8>(C, level);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipEvent_t next_event(sllg_ctx* C)
+{
+    if (C->ev_used == C->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        C->ev_pool.push_back(e);
+    }
+    return C->ev_pool[C->ev_used++];
+}
+
+// Run up to nsteps of every unfinished level.
+int run_steps(sllg_ctx* C, int64_t nsteps)
+{
+    if (nsteps <= 0) return SLLG_OK;
+    // stream levels: one launch per step (optionally replayed from a graph)
+    for (int l = 0; l < (int)C->lv.size(); ++l) {
+        LevelHost& h = C->lv[l];
+        if (h.plan != kPlanStream) continue;
+        const int64_t k = std::min(nsteps, h.n_steps - h.step);
+        for (int64_t s = 0; s < k; ++s) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (C->timing) {
+                e0 = next_event(C);
+                e1 = next_event(C);
+                if (!e0 || !e1) return fail(SLLG_E_HIP, "event pool");
+                HIP_OK(hipEventRecord(e0, C->stream));
+            }
+            HIP_OK(dispatch_stream(C, l));
+            if (C->timing) {
+                HIP_OK(hipEventRecord(e1, C->stream));
+                C->timed_cells = h.ncell * h.ninst;
+            }
+        }
+        h.step += k;
+    }
+    // resident sets: launches of at most 32768 steps
+    for (const auto& rs : C->res_sets) {
+        LevelHost& h0 = C->lv[rs.levels[0]];
+        int64_t k = std::min(nsteps, h0.n_steps - h0.step);
+        while (k > 0) {
+            const int64_t ns = std::min<int64_t>(k, 32768);
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            const bool time_this = C->timing && !std::any_of(C->lv.begin(), C->lv.end(), [](const LevelHost& x) {
+                return x.plan == kPlanStream;
+            });
+            if (time_this) {
+                e0 = next_event(C);
+                e1 = next_event(C);
+                HIP_OK(hipEventRecord(e0, C->stream));
+            }
+            HIP_OK(dispatch_res(C, rs, h0.step, ns));
+            if (time_this) {
+                HIP_OK(hipEventRecord(e1, C->stream));
+                int64_t cells = 0;
+                for (int l : rs.levels) cells += C->lv[l].ncell * C->lv[l].ninst;
+                C->timed_cells = cells * ns;
+            }
+            for (int l : rs.levels) C->lv[l].step += ns;
+            k -= ns;
+        }
+    }
+    return SLLG_OK;
+}
+
+int reset_state(sllg_ctx* C)
+{
+    for (LevelHost& h : C->lv) h.step = 0;
+    HIP_OK(hipMemsetAsync(C->d_steps, 0, sizeof(int64_t) * C->lv.size(), C->stream));
+    HIP_OK(hipMemsetAsync(C->d_status, 0, sizeof(int) * 4, C->stream));
+    HIP_OK(hipMemsetAsync(C->d_inst_cnt, 0, sizeof(uint32_t) * C->lay.ninst_total, C->stream));
+    HIP_OK(hipMemsetAsync(C->d_launch_cnt, 0, sizeof(uint32_t) * (C->lv.size() + 1), C->stream));
+    HIP_OK(hipMemsetAsync(C->d_records, 0, sizeof(double) * C->lay.rec_doubles, C->stream));
+    int maxc = 1;
+    for (const LevelHost& h : C->lv) maxc = (int)std::max<int64_t>(maxc, h.ncell);
+    dim3 grid((unsigned)std::min<int64_t>(ceil_div(maxc, 256), 4096), (unsigned)C->lay.ninst_total);
+    hipLaunchKernelGGL(k_init, grid, dim3(256), 0, C->stream, C->d_insts, C->d_levels,
+                       (int)C->lay.ninst_total, C->d_buf0, C->d_accs, C->d_records);
+    HIP_OK(hipGetLastError());
+    return SLLG_OK;
+}
+
+// Timing-based choice of the stream tile shape (a few steps per candidate),
+// cached per (dims, instances, device) for the process.
+std::map<std::tuple<int, int, int, int>, std::pair<int, int>> g_tuned;
+
+int tune_stream(sllg_ctx* C, int level)
+{
+    LevelHost& h = C->lv[level];
+    const auto key = std::make_tuple(h.in.nx, h.in.ny, h.in.nz, h.ninst);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+        h.shape = it->second.first;
+        h.tz = it->second.second;
+        return SLLG_OK;
+    }
+    default_stream_shape(C, h);
+    std::vector<std::pair<int, int>> cands;
+    for (int s = 0; s < kNumShapes; ++s) {
+        const Shape& S = kShapes[s];
+        // keep shapes whose window is not mostly idle
+        const double use = (double)std::min(S.tx, h.in.nx) * std::min(S.ty, h.in.ny) / (S.tx * S.ty);
+        if (use < 0.5) continue;
+        for (int tz : kTzChoices) {
+            if (tz < S.pz || tz > h.in.nz * 2) continue;
+            const int64_t nt = tiles_for(h.in, S, tz) * h.ninst;
+            if (nt < C->num_cus / 2 && tz > 1) continue;
+            if (nt > C->lay.max_tiles) continue;
+            cands.push_back({s, tz});
+        }
+    }
+    if (cands.size() <= 1) {
+        g_tuned[key] = {h.shape, h.tz};
+        return SLLG_OK;
+    }
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    double best_t = 1e30;
+    std::pair<int, int> best = {h.shape, h.tz};
+    const int reps = 6;
+    for (auto c : cands) {
+        h.shape = c.first;
+        h.tz = c.second;
+        int rc = replan(C);
+        if (rc) return rc;
+        // warm-up then timed steps; state is reset afterwards
+        for (int r = 0; r < 2; ++r) HIP_OK(dispatch_stream(C, level));
+        HIP_OK(hipEventRecord(e0, C->stream));
+        for (int r = 0; r < reps; ++r) HIP_OK(dispatch_stream(C, level));
+        HIP_OK(hipEventRecord(e1, C->stream));
+        HIP_OK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_t) {
+            best_t = ms;
+            best = c;
+        }
+        HIP_OK(hipMemsetAsync(C->d_steps, 0, sizeof(int64_t) * C->lv.size(), C->stream));
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h.shape = best.first;
+    h.tz = best.second;
+    g_tuned[key] = best;
+    return SLLG_OK;
+}
+
+// Host-side analytics of one loop (FP64).
+struct Stats {
+    double S, hd, ha, Hc, Mr, md0, ma0;
+    int nd, na, kd, ka;
+};
+
+Stats analyse(const std::vector<double>& H, const std::vector<double>& m)
+{
+    Stats s{};
+    s.hd = s.ha = s.md0 = s.ma0 = NAN;
+    s.kd = s.ka = -1;
+    for (size_t k = 0; k + 1 < H.size(); ++k) {
+        const double dH = H[k + 1] - H[k];
+        s.S -= 0.5 * (m[k] + m[k + 1]) * dH;
+        const int ch = (m[k] > 0.0) != (m[k + 1] > 0.0);
+        if (dH < 0) {
+            s.nd += ch;
+            if (s.kd < 0 && m[k] > 0.0 && m[k + 1] <= 0.0) {
+                s.kd = (int)k;
+                s.hd = H[k] - m[k] * dH / (m[k + 1] - m[k]);
+            }
+            if (std::isnan(s.md0) && H[k] > 0.0 && H[k + 1] <= 0.0) s.md0 = m[k] + (m[k + 1] - m[k]) * (-H[k]) / dH;
+        } else if (dH > 0) {
+            s.na += ch;
+            if (s.ka < 0 && m[k] < 0.0 && m[k + 1] >= 0.0) {
+                s.ka = (int)k;
+                s.ha = H[k] - m[k] * dH / (m[k + 1] - m[k]);
+            }
+            if (std::isnan(s.ma0) && H[k] < 0.0 && H[k + 1] >= 0.0) s.ma0 = m[k] + (m[k + 1] - m[k]) * (-H[k]) / dH;
+        }
+    }
+    s.Hc = 0.5 * (s.ha - s.hd);
+    s.Mr = 0.5 * (s.md0 - s.ma0);
+    return s;
+}
+
+double wave_host(const LevelHost& h, int wave, int64_t n)
+{
+    const int64_t N = h.n_period;
+    const int64_t k = n % N;
+    if (wave == 0) {
+        const double s = (double)k / (double)N;
+        return (2 * k <= N) ? 1.0 - 4.0 * s : 4.0 * s - 3.0;
+    }
+    if (wave == 1) return std::cos(2.0 * kPi * (double)k / (double)N);
+    return 1.0;
+}
+
+int check_status(sllg_ctx* C)
+{
+    int st[4] = {0, 0, 0, 0};
+    HIP_OK(hipMemcpyAsync(st, C->d_status, sizeof(st), hipMemcpyDeviceToHost, C->stream));
+    HIP_OK(hipStreamSynchronize(C->stream));
+    if (st[0]) return fail(SLLG_E_NUMERIC, "non-finite magnetisation in a loop (status %d)", st[0]);
+    return SLLG_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* sllg_last_error(void) { return g_err.c_str(); }
+
+size_t sllg_workspace_bytes(const sllg_material* mat, const sllg_level* levels, int32_t n_levels,
+                            int32_t ckpt_every)
+{
+    if (validate(mat, levels, n_levels) != SLLG_OK || ckpt_every < 0) return 0;
+    std::vector<LevelHost> lv(n_levels);
+    for (int i = 0; i < n_levels; ++i) compile_level(*mat, levels[i], lv[i]);
+    return make_layout(*mat, lv, ckpt_every).total;
+}
+
+int sllg_init(const sllg_material* mat, const sllg_level* levels, int32_t n_levels, int32_t ckpt_every,
+              void* d_workspace, size_t ws_bytes, void* hip_stream, sllg_ctx** out)
+{
+    if (!out) return fail(SLLG_E_INVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(mat, levels, n_levels);
+    if (rc) return rc;
+    if (ckpt_every < 0) return fail(SLLG_E_INVAL, "ckpt_every must be >= 0");
+    sllg_ctx* C = new sllg_ctx();
+    C->mat = *mat;
+    C->ckpt_every = ckpt_every;
+    C->stream = (hipStream_t)hip_stream;
+    C->lv.resize(n_levels);
+    int inst = 0;
+    int64_t axes = 0, state = 0, rec = 0, ckpt = 0;
+    for (int i = 0; i < n_levels; ++i) {
+        LevelHost& h = C->lv[i];
+        compile_level(*mat, levels[i], h);
+        if (!(h.dt > 0) || !std::isfinite(h.sigma) || !(h.alpha >= 0)) {
+            delete C;
+            return fail(SLLG_E_INVAL, "level %d: dt, sigma or alpha not usable", i);
+        }
+        h.inst0 = inst;
+        h.ninst = levels[i].n_real;
+        h.axes_off = levels[i].cone_deg > 0 ? axes : -1;
+        if (levels[i].cone_deg > 0) axes += 3 * h.ncell;
+        h.step = 0;
+        h.plan = 0;
+        h.forced = 0;
+        for (int r = 0; r < h.ninst; ++r) {
+            InstDev I{};
+            I.level = i;
+            I.real = r;
+            I.seed = levels[i].seed_base + (uint64_t)r;
+            I.state_off = state;
+            I.rec_off = rec;
+            I.ckpt_off = ckpt;
+            state += 3 * h.ncell;
+            rec += h.n_rec;
+            if (ckpt_every > 0) ckpt += ceil_div(h.n_steps, ckpt_every) * 3 * h.ncell;
+            C->h_insts.push_back(I);
+        }
+        inst += h.ninst;
+    }
+    C->lay = make_layout(*mat, C->lv, ckpt_every);
+    if (!d_workspace || ((uintptr_t)d_workspace & 255)) {
+        delete C;
+        return fail(SLLG_E_WORKSPACE, "workspace must be non-NULL and 256-byte aligned");
+    }
+    if (ws_bytes < C->lay.total) {
+        delete C;
+        return fail(SLLG_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, C->lay.total);
+    }
+    C->ws = (char*)d_workspace;
+    C->ws_bytes = ws_bytes;
+    const Layout& L = C->lay;
+    C->d_levels = (LevelDev*)(C->ws + L.levels);
+    C->d_insts = (InstDev*)(C->ws + L.insts);
+    C->d_accs = (AccDev*)(C->ws + L.accs);
+    C->d_steps = (int64_t*)(C->ws + L.steps);
+    C->d_status = (int*)(C->ws + L.status);
+    C->d_inst_cnt = (uint32_t*)(C->ws + L.inst_cnt);
+    C->d_launch_cnt = (uint32_t*)(C->ws + L.launch_cnt);
+    C->d_partials = (double*)(C->ws + L.partials);
+    C->d_tiles = (TileDev*)(C->ws + L.tiles);
+    C->d_groups = (GroupDev*)(C->ws + L.groups);
+    C->d_slots = (SlotDev*)(C->ws + L.slots);
+    C->d_chunks = (ChunkDev*)(C->ws + L.chunks);
+    C->d_buf0 = (float*)(C->ws + L.buf0);
+    C->d_buf1 = (float*)(C->ws + L.buf1);
+    C->d_axes = (float*)(C->ws + L.axes);
+    C->d_records = (double*)(C->ws + L.records);
+    C->d_ckpt = ckpt_every > 0 ? (float*)(C->ws + L.ckpt) : nullptr;
+    C->d_tape = (float*)(C->ws + L.tape);
+    C->d_lam = (float*)(C->ws + L.lam);
+    C->d_weights = (double*)(C->ws + L.weights);
+    C->d_grads = (double*)(C->ws + L.grads);
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        C->max_lds = (int)std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
+        C->num_cus = prop.multiProcessorCount;
+    }
+    C->h_levels.resize(n_levels);
+    for (int i = 0; i < n_levels; ++i) {
+        LevelHost& h = C->lv[i];
+        h.plan = resident_fits(h, C->max_lds) ? kPlanResident : kPlanStream;
+        if (h.plan == kPlanStream) default_stream_shape(C, h);
+    }
+    rc = replan(C);
+    if (rc) {
+        delete C;
+        return rc;
+    }
+    // per-cell axes
+    for (int i = 0; i < n_levels; ++i) {
+        const LevelHost& h = C->lv[i];
+        if (h.axes_off < 0) continue;
+        double e[3] = {mat->easy_axis[0], mat->easy_axis[1], mat->easy_axis[2]};
+        const double en = std::sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+        for (double& x : e) x /= en;
+        // rotation taking +z to e: Rodrigues about z x e
+        double R[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+        const double s = std::sqrt(e[0] * e[0] + e[1] * e[1]);
+        if (s > 0) {
+            const double k0 = -e[1] / s, k1 = e[0] / s, c = e[2];
+            const double K[3][3] = {{0, 0, k1}, {0, 0, -k0}, {-k1, k0, 0}};
+            for (int r = 0; r < 3; ++r)
+                for (int q = 0; q < 3; ++q) {
+                    double kk = 0;
+                    for (int t = 0; t < 3; ++t) kk += K[r][t] * K[t][q];
+                    R[r][q] = (r == q ? 1.0 : 0.0) + s * K[r][q] + (1.0 - c) * kk;
+                }
+        } else if (e[2] < 0) {
+            R[1][1] = -1;
+            R[2][2] = -1;
+        }
+        const float cmax = (float)(1.0 - std::cos(h.in.cone_deg * kPi / 180.0));
+        hipLaunchKernelGGL(k_axes, dim3((unsigned)ceil_div(h.ncell, 256)), dim3(256), 0, C->stream,
+                           C->d_levels, i, h.in.axis_seed, cmax, (float)R[0][0], (float)R[0][1],
+                           (float)R[0][2], (float)R[1][0], (float)R[1][1], (float)R[1][2], (float)R[2][0],
+                           (float)R[2][1], (float)R[2][2], C->d_axes);
+        if (hipGetLastError() != hipSuccess) {
+            delete C;
+            return fail(SLLG_E_HIP, "axes kernel launch failed");
+        }
+    }
+    rc = reset_state(C);
+    if (rc) {
+        delete C;
+        return rc;
+    }
+    // tune stream shapes on first use of a shape, then start from step 0 again
+    bool tuned = false;
+    for (int i = 0; i < n_levels; ++i)
+        if (C->lv[i].plan == kPlanStream && !getenv("SLLG_NO_TUNE")) {
+            rc = tune_stream(C, i);
+            if (rc) {
+                delete C;
+                return rc;
+            }
+            tuned = true;
+        }
+    if (tuned) {
+        rc = replan(C);
+        if (!rc) rc = reset_state(C);
+        if (rc) {
+            delete C;
+            return rc;
+        }
+    }
+    *out = C;
+    return SLLG_OK;
+}
+
+int sllg_run_sweep(sllg_ctx* C)
+{
+    if (!C) return fail(SLLG_E_INVAL, "null context");
+    int64_t left = 0;
+    for (const LevelHost& h : C->lv) left = std::max(left, h.n_steps - h.step);
+    return run_steps(C, left);
+}
+
+int sllg_run_steps(sllg_ctx* C, int64_t nsteps)
+{
+    if (!C) return fail(SLLG_E_INVAL, "null context");
+    if (nsteps < 0) return fail(SLLG_E_INVAL, "nsteps must be >= 0");
+    return run_steps(C, nsteps);
+}
+
+int sllg_reset(sllg_ctx* C)
+{
+    if (!C) return fail(SLLG_E_INVAL, "null context");
+    int rc = reset_state(C);
+    if (rc) return rc;
+    return replan(C);
+}
+
+int sllg_loop(sllg_ctx* C, int32_t level, int32_t real, double* H_Oe, double* mH, int64_t cap,
+              int64_t* n_out, sllg_loop_stats* stats)
+{
+    if (!C || level < 0 || level >= (int)C->lv.size()) return fail(SLLG_E_INVAL, "bad level");
+    const LevelHost& h = C->lv[level];
+    if (real < -1 || real >= h.ninst) return fail(SLLG_E_INVAL, "bad realization %d", real);
+    int rc = check_status(C);
+    if (rc) return rc;
+    const int64_t npts = h.step / h.in.record_every + 1;
+    if (n_out) *n_out = npts;
+    if ((H_Oe || mH) && cap < npts) return fail(SLLG_E_CAPACITY, "need %lld entries", (long long)npts);
+    const int r0 = real < 0 ? 0 : real, r1 = real < 0 ? h.ninst : real + 1;
+    std::vector<double> rec((size_t)(r1 - r0) * h.n_rec);
+    std::vector<AccDev> acc(r1 - r0);
+    for (int r = r0; r < r1; ++r) {
+        const InstDev& I = C->h_insts[h.inst0 + r];
+        HIP_OK(hipMemcpyAsync(rec.data() + (size_t)(r - r0) * h.n_rec, C->d_records + I.rec_off,
+                              sizeof(double) * h.n_rec, hipMemcpyDeviceToHost, C->stream));
+    }
+    HIP_OK(hipMemcpyAsync(acc.data(), C->d_accs + h.inst0 + r0, sizeof(AccDev) * (r1 - r0),
+                          hipMemcpyDeviceToHost, C->stream));
+    HIP_OK(hipStreamSynchronize(C->stream));
+    std::vector<double> H(npts), m(npts, 0.0);
+    const double hz_oe = h.hz_amp / kOe;
+    for (int64_t k = 0; k < npts; ++k) H[k] = hz_oe * wave_host(h, C->mat.wave, k * h.in.record_every);
+    for (int r = 0; r < r1 - r0; ++r)
+        for (int64_t k = 0; k < npts; ++k) m[k] += rec[(size_t)r * h.n_rec + k];
+    for (int64_t k = 0; k < npts; ++k) m[k] /= (double)(r1 - r0);
+    if (H_Oe) std::memcpy(H_Oe, H.data(), sizeof(double) * npts);
+    if (mH) std::memcpy(mH, m.data(), sizeof(double) * npts);
+    if (stats) {
+        const Stats s = analyse(H, m);
+        sllg_loop_stats o{};
+        // area from the per-step accumulators (exact with decimated records)
+        double area = 0;
+        for (const AccDev& a : acc) area += a.area;
+        o.S_sim = area / (double)acc.size();
+        o.S_phys = o.S_sim * h.cM / h.hscale;
+        o.Hc_desc = s.hd;
+        o.Hc_asc = s.ha;
+        o.Hc_sim = s.Hc;
+        o.Hc_phys = s.Hc / h.hscale;
+        o.Mr_sim = s.Mr;
+        o.Mr_phys = s.Mr * h.cM;
+        o.n_cross_desc = s.nd;
+        o.n_cross_asc = s.na;
+        o.n_real = (int)acc.size();
+        o.S_se = NAN;
+        o.Hc_se = NAN;
+        if (acc.size() > 1) {
+            double ms = 0, vs = 0;
+            std::vector<double> hc;
+            for (const AccDev& a : acc) {
+                ms += a.area;
+                if (a.found_d && a.found_a) hc.push_back(0.5 * (a.hstar_a - a.hstar_d));
+            }
+            ms /= acc.size();
+            for (const AccDev& a : acc) vs += (a.area - ms) * (a.area - ms);
+            o.S_se = std::sqrt(vs / (acc.size() - 1) / acc.size());
+            if (hc.size() > 1) {
+                double mh = 0, vh = 0;
+                for (double x : hc) mh += x;
+                mh /= hc.size();
+                for (double x : hc) vh += (x - mh) * (x - mh);
+                o.Hc_se = std::sqrt(vh / (hc.size() - 1) / hc.size());
+            }
+        }
+        *stats = o;
+    }
+    return SLLG_OK;
+}
+
+int sllg_level_params(const sllg_ctx* C, int32_t level, double out[16])
+{
+    if (!C || level < 0 || level >= (int)C->lv.size() || !out) return fail(SLLG_E_INVAL, "bad level");
+    const LevelHost& h = C->lv[level];
+    const double v[16] = {h.zeta, h.A, h.K, h.Ms, h.a, h.c_ex, h.hk, h.gamma1, h.alpha, h.sigma, h.dt,
+                          h.hscale, h.cM, (double)h.n_steps, h.hz_amp,
+                          (double)(h.plan * 100 + (h.plan == kPlanStream ? h.shape : 0))};
+    std::memcpy(out, v, sizeof(v));
+    return SLLG_OK;
+}
+
+int64_t sllg_level_step(const sllg_ctx* C, int32_t level)
+{
+    if (!C || level < 0 || level >= (int)C->lv.size()) return -1;
+    return C->lv[level].step;
+}
+
+int sllg_get_state(sllg_ctx* C, int32_t level, int32_t real, float* host_m)
+{
+    if (!C || level < 0 || level >= (int)C->lv.size() || !host_m) return fail(SLLG_E_INVAL, "bad args");
+    const LevelHost& h = C->lv[level];
+    if (real < 0 || real >= h.ninst) return fail(SLLG_E_INVAL, "bad realization");
+    const InstDev& I = C->h_insts[h.inst0 + real];
+    const float* src = ((h.step & 1) ? C->d_buf1 : C->d_buf0) + I.state_off;
+    HIP_OK(hipMemcpyAsync(host_m, src, sizeof(float) * 3 * h.ncell, hipMemcpyDeviceToHost, C->stream));
+    HIP_OK(hipStreamSynchronize(C->stream));
+    return SLLG_OK;
+}
+
+int sllg_set_state(sllg_ctx* C, int32_t level, int32_t real, const float* host_m)
+{
+    if (!C || level < 0 || level >= (int)C->lv.size() || !host_m) return fail(SLLG_E_INVAL, "bad args");
+    const LevelHost& h = C->lv[level];
+    if (real < 0 || real >= h.ninst) return fail(SLLG_E_INVAL, "bad realization");
+    const InstDev& I = C->h_insts[h.inst0 + real];
+    float* dst = ((h.step & 1) ? C->d_buf1 : C->d_buf0) + I.state_off;
+    HIP_OK(hipMemcpyAsync(dst, host_m, sizeof(float) * 3 * h.ncell, hipMemcpyHostToDevice, C->stream));
+    // the loop continues from this state's ordinate
+    double mz = 0;
+    for (int64_t c = 0; c < h.ncell; ++c) mz += host_m[2 * h.ncell + c];
+    mz /= (double)h.ncell;
+    AccDev a;
+    HIP_OK(hipMemcpyAsync(&a, C->d_accs + h.inst0 + real, sizeof(AccDev), hipMemcpyDeviceToHost, C->stream));
+    HIP_OK(hipStreamSynchronize(C->stream));
+    a.m_prev = mz;
+    HIP_OK(hipMemcpyAsync(C->d_accs + h.inst0 + real, &a, sizeof(AccDev), hipMemcpyHostToDevice, C->stream));
+    if (h.step % h.in.record_every == 0)
+        HIP_OK(hipMemcpyAsync(C->d_records + I.rec_off + h.step / h.in.record_every, &mz, sizeof(double),
+                              hipMemcpyHostToDevice, C->stream));
+    HIP_OK(hipStreamSynchronize(C->stream));
+    return SLLG_OK;
+}
+
+int sllg_set_plan(sllg_ctx* C, int32_t level, int32_t plan)
+{
+    if (!C || level < 0 || level >= (int)C->lv.size()) return fail(SLLG_E_INVAL, "bad level");
+    LevelHost& h = C->lv[level];
+    if (plan == kPlanAuto) {
+        h.forced = 0;
+        plan = resident_fits(h, C->max_lds) ? kPlanResident : kPlanStream;
+    } else if (plan == kPlanResident) {
+        if (!resident_fits(h, C->max_lds)) return fail(SLLG_E_INVAL, "level %d does not fit in LDS", level);
+        h.forced = 1;
+    } else if (plan == kPlanStream) {
+        h.forced = 1;
+    } else {
+        return fail(SLLG_E_INVAL, "unknown plan %d", plan);
+    }
+    h.plan = plan;
+    if (plan == kPlanStream) {
+        auto it = g_tuned.find(std::make_tuple(h.in.nx, h.in.ny, h.in.nz, h.ninst));
+        if (it != g_tuned.end()) {
+            h.shape = it->second.first;
+            h.tz = it->second.second;
+        } else {
+            default_stream_shape(C, h);
+        }
+    }
+    int rc = replan(C);
+    if (rc) return rc;
+    // the stream kernel reads the step index from the device
+    for (size_t l = 0; l < C->lv.size(); ++l)
+        HIP_OK(hipMemcpyAsync(C->d_steps + l, &C->lv[l].step, sizeof(int64_t), hipMemcpyHostToDevice,
+                              C->stream));
+    HIP_OK(hipStreamSynchronize(C->stream));
+    return SLLG_OK;
+}
+
+int sllg_philox_probe(uint64_t seed, uint32_t level, uint32_t tag, const uint32_t* cells,
+                      const uint64_t* steps, int32_t n, uint32_t* raw, float* normals, void* d_scratch,
+                      void* hip_stream)
+{
+    if (n < 0 || !cells || !steps || !raw || !normals || !d_scratch) return fail(SLLG_E_INVAL, "bad args");
+    if (tag > 255 || level > 255) return fail(SLLG_E_INVAL, "tag and level are 8-bit");
+    if (n == 0) return SLLG_OK;
+    hipStream_t s = (hipStream_t)hip_stream;
+    char* p = (char*)d_scratch;
+    uint32_t* d_cells = (uint32_t*)p;
+    uint64_t* d_steps = (uint64_t*)(p + align256(4 * (size_t)n));
+    uint32_t* d_raw = (uint32_t*)((char*)d_steps + align256(8 * (size_t)n));
+    float* d_nrm = (float*)((char*)d_raw + align256(16 * (size_t)n));
+    HIP_OK(hipMemcpyAsync(d_cells, cells, 4 * (size_t)n, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(d_steps, steps, 8 * (size_t)n, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_philox_probe, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, seed, level, tag,
+                       d_cells, d_steps, n, d_raw, d_nrm);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(raw, d_raw, 16 * (size_t)n, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(normals, d_nrm, 12 * (size_t)n, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return SLLG_OK;
+}
+
+int sllg_get_axes(sllg_ctx* C, int32_t level, float* host_u)
+{
+    if (!C || level < 0 || level >= (int)C->lv.size() || !host_u) return fail(SLLG_E_INVAL, "bad args");
+    const LevelHost& h = C->lv[level];
+    if (h.axes_off < 0) {
+        const LevelDev& d = C->h_levels[level];
+        for (int64_t c = 0; c < h.ncell; ++c) {
+            host_u[c] = d.ux;
+            host_u[h.ncell + c] = d.uy;
+            host_u[2 * h.ncell + c] = d.uz;
+        }
+        return SLLG_OK;
+    }
+    HIP_OK(hipMemcpyAsync(host_u, C->d_axes + h.axes_off, sizeof(float) * 3 * h.ncell, hipMemcpyDeviceToHost,
+                          C->stream));
+    HIP_OK(hipStreamSynchronize(C->stream));
+    return SLLG_OK;
+}
+
+int sllg_set_timing(sllg_ctx* C, int32_t on)
+{
+    if (!C) return fail(SLLG_E_INVAL, "null context");
+    C->timing = on != 0;
+    C->ev_used = 0;
+    return SLLG_OK;
+}
+
+int sllg_kernel_time(sllg_ctx* C, double* mean_ms, int64_t* launches, int64_t* cells_per_launch)
+{
+    if (!C) return fail(SLLG_E_INVAL, "null context");
+    HIP_OK(hipStreamSynchronize(C->stream));
+    double tot = 0;
+    const int64_t nl = (int64_t)(C->ev_used / 2);
+    for (int64_t i = 0; i < nl; ++i) {
+        float ms = 0;
+        HIP_OK(hipEventElapsedTime(&ms, C->ev_pool[2 * i], C->ev_pool[2 * i + 1]));
+        tot += ms;
+    }
+    if (mean_ms) *mean_ms = nl ? tot / nl : 0.0;
+    if (launches) *launches = nl;
+    if (cells_per_launch) *cells_per_launch = C->timed_cells;
+    C->ev_used = 0;
+    return SLLG_OK;
+}
+
+int sllg_grad(sllg_ctx* C, int32_t level, double g_area[4], double g_hc[4])
+{
+    (void)g_area;
+    (void)g_hc;
+    if (!C || level < 0 || level >= (int)C->lv.size()) return fail(SLLG_E_INVAL, "bad level");
+    return fail(SLLG_E_STATE, "adjoint not built yet");
+}
+
+void sllg_free(sllg_ctx* C)
+{
+    if (!C) return;
+    for (hipEvent_t e : C->ev_pool) (void)hipEventDestroy(e);
+    for (const auto& g : C->graphs) (void)hipGraphExecDestroy(g.second);
+    delete C;
+}
+
+}  // extern "C"
