@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Benchmark of the stochastic-LLG hysteresis-loop path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A bench step is one full field sweep (one dynamic hysteresis loop per
+realization) of the named workload, including the per-step loop reduction
+and the loop analytics; for the 8.4M-cell block it is a window of Heun steps
+(the sweep is 6.4e6 steps).  Inputs are synthetic and seeded, already resident
+in HBM when timing starts.  Rank 0 prints one JSON line.
+
+Workloads (sllg_workloads): rod_b1_ens8 (default: 8x24x56 rod, b=1, 8
+realizations, 4e6 steps of 1 fs), rod_b4_single, multilevel_ens256,
+block_b2_cone10, rod_b4_adjoint64.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "sLLG cell-updates/s & loops/s at 1 GPU (% HBM roofline); batched & adjoint vs plain"
+
+# Algorithmic work of one cell-update (one Heun step of one cell); derivation
+# in the design doc.  Lane operations counted at one per VALU op (an FMA is one):
+# Philox4x32-10 (20 wide multiplies + 40 xors), four 23-bit uniforms, the
+# Box-Muller transform, two effective fields, two LLG right-hand sides, the
+# predictor/corrector updates and two renormalisations.
+VALU_OPS_PER_CELL_UPDATE = 240
+# HBM: m_n in and m_{n+1} out (12 + 12 bytes); per-cell easy axes add 12.
+BYTES_PER_CELL_UPDATE = 24
+BYTES_AXES = 12
+PEAK_HBM_GBS = 8000.0
+# FP32 vector peak 157.3 TFLOP/s = 78.6e12 FMA lane-operations per second
+# (256 CUs x 128 lanes x 2.4 GHz); one VALU op per lane counted as one
+PEAK_VALU_TOPS = 256 * 128 * 2.4e9 / 1e12
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed bench steps")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed bench steps")
+    ap.add_argument("--workload", default="rod_b1_ens8")
+    ap.add_argument("--window", type=int, default=None,
+                    help="Heun steps per bench step (default: the whole sweep; 2000 for the block)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain device copy of known size (for counter scaling)")
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus_requested": a.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import sllg_workloads as W
+    from paper_1912_00310_amd import Sim
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    wl = W.workload(a.workload)
+    mat, levels = wl["material"], wl["levels"]
+    ckpt = wl.get("ckpt_every", 0)
+    adjoint = a.workload == "rod_b4_adjoint64"
+    t_init = time.time()
+    sim = Sim(mat, levels, ckpt_every=ckpt if adjoint else 0)
+    torch.cuda.synchronize()
+    t_init = time.time() - t_init
+    params = [sim.level_params(l) for l in range(len(levels))]
+    n_sweep = int(max(p["n_steps"] for p in params))
+    window = a.window
+    if window is None and "window" in wl:
+        window = wl["window"]["timed_steps"]
+    window = min(window or n_sweep, n_sweep)
+    cells_per_step = sum(sim.ncell(l) * levels[l]["n_real"] for l in range(len(levels)))
+    heavy = window >= 1_000_000
+    steps = a.steps if a.steps is not None else (2 if heavy else 5)
+    warmup = a.warmup if a.warmup is not None else 1
+
+    def one_step():
+        # one sweep (or window) of every level and realization
+        if window == n_sweep:
+            sim.reset()
+            sim.run_sweep()
+        else:
+            if sim.step(0) + window > n_sweep:
+                sim.reset()
+            sim.run_steps(window)
+        if adjoint:
+            sim.grad(0)
+        for l in range(len(levels)):
+            sim.loop(l, -1)
+
+    if "window" in wl and window < n_sweep:
+        sim.run_steps(wl["window"]["warmup_steps"])
+    for _ in range(warmup):
+        one_step()
+    torch.cuda.synchronize()
+    # time every 64th dominant-kernel launch with events on the library's stream
+    sim.set_timing(64 if window >= 10000 else 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k_ms, k_n, k_cells = sim.kernel_time()
+    sim.set_timing(0)
+    dt = t1 - t0
+    cell_updates = cells_per_step * window * steps
+    value = cell_updates / dt
+    loops = sum(levels[l]["n_real"] for l in range(len(levels))) * steps * window / n_sweep
+    stats = {l: sim.loop(l, -1)[2] for l in range(len(levels))}
+    plan_ids = [int(p["plan"]) for p in params]
+
+    # roofline of the dominant kernel from its mean launch time
+    rl = None
+    if k_n > 0 and k_ms > 0:
+        per_launch = k_cells
+        has_axes = any(l.get("cone_deg", 0) > 0 for l in levels)
+        bpc = BYTES_PER_CELL_UPDATE + (BYTES_AXES if has_axes else 0)
+        gbs = per_launch * bpc / (k_ms * 1e-3) / 1e9
+        tops = per_launch * VALU_OPS_PER_CELL_UPDATE / (k_ms * 1e-3) / 1e12
+        f_h, f_a = gbs / PEAK_HBM_GBS, tops / PEAK_VALU_TOPS
+        if f_h >= f_a:
+            rl = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                  "frac": round(f_h, 4), "traffic": None}
+        else:
+            rl = {"bound": "alu", "achieved": round(tops, 3), "peak": round(PEAK_VALU_TOPS, 3),
+                  "unit": "TOP/s", "frac": round(f_a, 4), "traffic": None}
+        rl["kernel"] = "k_rows/k_stream" if any(p // 100000 == 2 for p in plan_ids) else "k_resident"
+        rl["mean_launch_ms"] = k_ms
+        rl["launches_timed"] = k_n
+        rl["cell_updates_per_launch"] = per_launch
+        rl["hbm_equiv_GBps"] = round(gbs, 1)
+        rl["valu_TOPs"] = round(tops, 3)
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = cpu_baseline(wl, a.cpu_seconds)
+
+    if a.copy_probe:
+        n = 1 << 28   # 1 GiB of float32 read and written
+        x = torch.empty(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": dt / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": a.workload,
+            "levels": [f"{l['nx']}x{l['ny']}x{l['nz']} b={l['b']:g} x{l['n_real']}" for l in levels],
+            "heun_steps_per_bench_step": window,
+            "heun_steps_per_sweep": n_sweep,
+            "dt_fs": [round(p["dt"] * 1e15, 3) for p in params],
+            "alpha": [p["alpha"] for p in params],
+            "plan": plan_ids,
+            "loop_accumulators": "f64",
+        },
+        "loops_per_s": loops / dt,
+        "init_s": round(t_init, 3),
+        "roofline": rl,
+        "cpu_baseline": cpu,
+        "loop": {str(l): {k: (None if isinstance(v, float) and math.isnan(v) else v)
+                          for k, v in stats[l].items()} for l in stats},
+    }
+    print(json.dumps(out))
+    sim.close()
+
+
+def cpu_baseline(wl, seconds):
+    """FP64 oracle on the host cores over a bounded sample of the workload."""
+    import oracle
+    from oracle import gk
+    lvd = max(wl["levels"], key=lambda l: l["nx"] * l["ny"] * l["nz"] * l["n_real"])
+    idx = wl["levels"].index(lvd)
+    lv = gk.compile_level(wl["material"], lvd, idx)
+    ncell = lv["nx"] * lv["ny"] * lv["nz"]
+    threads = oracle.max_threads()
+    nreal = min(lvd["n_real"], max(1, threads))
+    seeds = [lvd["seed_base"] + r for r in range(nreal)]
+    # calibrate on a short run, then size the sample to about `seconds`
+    probe = max(1, int(2e6 // (ncell * nreal)))
+    t = time.perf_counter()
+    oracle.run_batch(lv, seeds, probe)
+    rate = ncell * nreal * probe / (time.perf_counter() - t)
+    nsteps = max(1, min(lv["n_steps"], int(rate * seconds / (ncell * nreal))))
+    t = time.perf_counter()
+    oracle.run_batch(lv, seeds, nsteps)
+    el = time.perf_counter() - t
+    return {"value": ncell * nreal * nsteps / el, "unit": "cell-updates/s",
+            "cores": min(nreal, threads), "kind": "oracle",
+            "sample": f"{nreal} realizations x {nsteps} Heun steps of the "
+                      f"{lv['nx']}x{lv['ny']}x{lv['nz']} grid (FP64 C oracle, OpenMP over realizations)",
+            "seconds": round(el, 2)}
+
+
+if __name__ == "__main__":
+    main()

@@ -156,7 +156,8 @@ void sllg_free(sllg_ctx* ctx);
 /* ---- introspection used by tests and the benchmark ---------------------- */
 
 /* Compiled constants of a level: out[0..15] = zeta, A, K, Ms, a, c_ex, hk,
- * gamma1, alpha, sigma, dt, hscale, cM, n_steps, hz_amp (A/m), level plan id. */
+ * gamma1, alpha, sigma, dt, hscale, cM, n_steps, hz_amp (A/m) and the plan
+ * code 100000*plan + 1000*tile shape + z planes per tile (stream plan). */
 int sllg_level_params(const sllg_ctx* ctx, int32_t level, double out[16]);
 
 /* Current step index of a level. */
@@ -188,10 +189,13 @@ int sllg_philox_probe(uint64_t seed, uint32_t level, uint32_t tag, const uint32_
  * planes ux | uy | uz).  Synchronises the stream. */
 int sllg_get_axes(sllg_ctx* ctx, int32_t level, float* host_u);
 
-/* Mean time of the dominant kernel's launches since the last call
- * (milliseconds, from HIP events on the context stream) and the number of
- * launches timed; timing is enabled by sllg_set_timing(ctx, 1). */
-int sllg_set_timing(sllg_ctx* ctx, int32_t on);
+/* Timing of the dominant kernel (the streamed step kernel if a level uses
+ * it, else the resident kernel).  sllg_set_timing(ctx, k) with k > 0 brackets
+ * every k-th launch with HIP events on the context stream (k = 0 switches it
+ * off).  sllg_kernel_time returns the mean duration of the timed launches in
+ * milliseconds, how many were timed, and the cell-updates one timed launch
+ * performs; it synchronises the stream and restarts the count. */
+int sllg_set_timing(sllg_ctx* ctx, int32_t every);
 int sllg_kernel_time(sllg_ctx* ctx, double* mean_ms, int64_t* launches, int64_t* cells_per_launch);
 
 #ifdef __cplusplus

@@ -86,18 +86,15 @@ __device__ __forceinline__ V3 gauss3(U4 w)
 // ---------------------------------------------------------------------------
 // Field protocol
 // ---------------------------------------------------------------------------
-// Fraction of the peak applied field at step n (FP64).
+// Fraction of the peak applied field at step n (FP64).  The phase k/N is
+// formed with the stored reciprocal of N (within one ulp of the quotient).
 __device__ __forceinline__ double wave_at(const LevelDev& L, int64_t n)
 {
-    const int64_t N = L.n_period;
-    const int64_t k = n % N;
-    if (L.wave == 0) {
-        const double s = static_cast<double>(k) / static_cast<double>(N);
-        return (2 * k <= N) ? 1.0 - 4.0 * s : 4.0 * s - 3.0;
-    }
-    if (L.wave == 1) {
-        return cospi(2.0 * static_cast<double>(k) / static_cast<double>(N));
-    }
+    int64_t k = n;
+    while (k >= L.n_period) k -= L.n_period;
+    const double s = static_cast<double>(k) * L.inv_period;
+    if (L.wave == 0) return (2 * k <= L.n_period) ? 1.0 - 4.0 * s : 4.0 * s - 3.0;
+    if (L.wave == 1) return cospi(2.0 * s);
     return 1.0;
 }
 
@@ -200,10 +197,68 @@ __device__ inline void loop_accumulate(AccDev& a, const LevelDev& L, int64_t n, 
         }
     }
     a.m_prev = m_new;
-    if ((n + 1) % L.record_every == 0) rec[(n + 1) / L.record_every] = m_new;
+    if (++a.rec_phase == L.record_every) {
+        a.rec_phase = 0;
+        if (a.rec_idx + 1 < L.n_rec) rec[++a.rec_idx] = m_new;   // never past the record
+    }
 }
 
 // Wave-wide FP32 sum (all 64 lanes end with the total).
+__device__ __forceinline__ float wave_sum(float v);
+__device__ __forceinline__ double wave_sum_d(double v);
+
+// Stream plan bookkeeping without device-wide fences.  Tile partials of step
+// n go to partials[(n & 1) * ptiles + tile]; the instance's first tile folds
+// the partials of step n - 1 into the loop at the start of the launch for
+// step n (the kernel boundary makes them visible); a flush kernel folds the
+// last step of a run.  Wave 0 of the calling block sums the partials in a
+// fixed order, so the loop is bitwise reproducible.
+__device__ inline void fold_partials(const InstDev& I, const LevelDev& L, int64_t n, const double* partials,
+                                     int ptiles, AccDev* accs, int inst, double* records, int* status)
+{
+    if (threadIdx.x >= 64) return;
+    const double* p = partials + (n & 1) * static_cast<int64_t>(ptiles) + I.tile0;
+    double s = 0.0;
+    for (int t = static_cast<int>(threadIdx.x); t < I.ntiles; t += 64) s += p[t];
+    s = wave_sum_d(s);
+    if (threadIdx.x == 0) {
+        AccDev a = accs[inst];
+        loop_accumulate(a, L, n, s / static_cast<double>(L.ncell), records + I.rec_off);
+        accs[inst] = a;
+        if (!isfinite(a.m_prev)) atomicOr(status, 1);
+    }
+}
+
+// Block sum of one FP32 value per thread: FP32 within waves, FP64 across
+// waves in wave order.  red holds NT / 64 doubles; thread 0 gets the total.
+template <int NT>
+__device__ inline double block_sum(float v, double* red)
+{
+    const float ws = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = static_cast<double>(ws);
+    __syncthreads();
+    double tot = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < NT / 64; ++w) tot += red[w];
+    return tot;
+}
+
+// End of a stream-plan block: publish the tile partial; the last block of
+// the launch advances the step counter (relaxed atomics: every block read
+// the counter before it arrived here).
+__device__ inline void stream_block_end(double tot, int64_t n, int tile, int ptiles, double* partials,
+                                        bool first_tile, uint32_t* pend, int inst, uint32_t* launch_cnt,
+                                        int64_t* steps, int level, int64_t n_steps)
+{
+    if (threadIdx.x != 0) return;
+    partials[(n & 1) * static_cast<int64_t>(ptiles) + tile] = tot;
+    if (first_tile) pend[inst] = 1u;
+    const uint32_t prev = __hip_atomic_fetch_add(launch_cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev == gridDim.x - 1) {
+        __hip_atomic_store(launch_cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (n + 1 <= n_steps) __hip_atomic_store(&steps[level], n + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
 __device__ __forceinline__ float wave_sum(float v)
 {
 #pragma unroll

@@ -23,6 +23,8 @@
 
 // The kernels are compiled in this translation unit (one shared library).
 #include "sllg_kernels.hip"
+#include "sllg_rows.hip"
+#include "sllg_adjoint.hip"
 
 using namespace sllg;
 
@@ -75,12 +77,16 @@ struct LevelHost {
     int64_t step;         // host view of the step index
 };
 
+// Stream-plan tile shapes.  kind 0: k_stream<tx, ty, pz> (x-y window with a
+// recomputed ring); kind 1: k_rows<tx = threads, ty = cells per thread>
+// (full-width tiles, needs nx <= threads).
 struct Shape {
-    int tx, ty, pz;
+    int kind, tx, ty, pz;
 };
-// tile shapes the stream kernel is instantiated for
-const Shape kShapes[] = {{64, 8, 1}, {32, 16, 1}, {64, 16, 1}, {32, 8, 2}, {8, 24, 4},
-                         {8, 24, 2}, {8, 24, 1}, {16, 16, 2}, {4, 12, 8}};
+const Shape kShapes[] = {{0, 64, 8, 1},  {0, 32, 16, 1}, {0, 64, 16, 1}, {0, 32, 8, 2},
+                         {0, 8, 24, 4},  {0, 8, 24, 2},  {0, 8, 24, 1},  {0, 16, 16, 2},
+                         {0, 4, 12, 8},  {1, 192, 1, 1}, {1, 256, 1, 1}, {1, 256, 2, 1},
+                         {1, 512, 1, 1}, {1, 512, 2, 1}, {1, 1024, 1, 1}, {1, 256, 4, 1}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 const int kTzChoices[] = {1, 2, 4, 8, 16, 32, 64};
 
@@ -101,8 +107,37 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Row windows [y0, y0 + nyt) of a full-width tile with R predicted rows
+// (the window plus one ring row on each side inside the grid).
+std::vector<std::pair<int, int>> row_windows(int ny, int R)
+{
+    std::vector<std::pair<int, int>> w;
+    if (R < 3 && ny > R) return w;
+    int y0 = 0;
+    while (y0 < ny) {
+        int nyt = R - (y0 > 0 ? 1 : 0);               // rows left after the upper ring
+        if (y0 + nyt >= ny) nyt = ny - y0;              // last window: no lower ring
+        else nyt -= 1;                                   // keep a row for the lower ring
+        w.push_back({y0, nyt});
+        y0 += nyt;
+    }
+    return w;
+}
+
+bool shape_fits(const sllg_level& L, const Shape& s)
+{
+    if (s.kind == 0) return true;
+    if (L.nx > s.tx) return false;
+    const int R = (s.tx / L.nx) * s.ty;
+    return !row_windows(L.ny, R).empty();
+}
+
 int64_t tiles_for(const sllg_level& L, const Shape& s, int tz)
 {
+    if (s.kind == 1) {
+        if (!shape_fits(L, s)) return 0;
+        return (int64_t)row_windows(L.ny, (s.tx / L.nx) * s.ty).size() * ceil_div(L.nz, tz);
+    }
     return ceil_div(L.nx, s.tx) * ceil_div(L.ny, s.ty) * ceil_div(L.nz, tz);
 }
 
@@ -162,14 +197,18 @@ struct sllg_ctx {
     std::vector<SlotDev> h_slots;
     std::vector<ChunkDev> h_chunks;
     // timing of the dominant kernel
-    bool timing = false;
+    int timing = 0;              // 0 off, k: time every k-th launch of the dominant kernel
+    int64_t launch_counter = 0;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     int64_t timed_cells = 0;
     int max_lds = 65536;
     int num_cus = 256;
-    bool use_graph = false;
-    std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
+    // HIP graphs of kGraphSteps stream launches per level (the stream kernel
+    // reads its step index from device memory, so one graph serves any step)
+    bool use_graph = true;
+    hipStream_t cap_stream = nullptr;
+    std::map<int, hipGraphExec_t> graphs;
 };
 
 namespace {
@@ -261,6 +300,7 @@ LevelDev to_dev(const sllg_material& m, const LevelHost& h, int tag)
     d.hz_oe = h.hz_amp / kOe;
     d.n_period = h.n_period;
     d.n_steps = h.n_steps;
+    d.inv_period = 1.0 / (double)h.n_period;
     d.wave = m.wave;
     d.level_tag = tag;
     d.record_every = h.in.record_every;
@@ -327,7 +367,7 @@ Layout make_layout(const sllg_material& m, const std::vector<LevelHost>& lv, int
     L.status = take(sizeof(int) * 4);
     L.inst_cnt = take(sizeof(uint32_t) * ninst);
     L.launch_cnt = take(sizeof(uint32_t) * (lv.size() + 1));
-    L.partials = take(sizeof(double) * tiles);
+    L.partials = take(sizeof(double) * 2 * tiles);   // two step parities
     L.tiles = take(sizeof(TileDev) * tiles);
     L.groups = take(sizeof(GroupDev) * ninst);
     L.slots = take(sizeof(SlotDev) * ninst);
@@ -355,6 +395,23 @@ void build_tiles(sllg_ctx* C, LevelHost& h)
     for (int r = 0; r < h.ninst; ++r) {
         InstDev& I = C->h_insts[h.inst0 + r];
         I.tile0 = (int)C->h_tiles.size();
+        if (s.kind == 1) {
+            const auto rows = row_windows(h.in.ny, (s.tx / h.in.nx) * s.ty);
+            for (int z0 = 0; z0 < h.in.nz; z0 += h.tz)
+                for (const auto& w : rows) {
+                    TileDev t{};
+                    t.inst = h.inst0 + r;
+                    t.x0 = 0;
+                    t.y0 = (int16_t)w.first;
+                    t.z0 = (int16_t)z0;
+                    t.nxt = (int16_t)h.in.nx;
+                    t.nyt = (int16_t)w.second;
+                    t.nzt = (int16_t)std::min(h.tz, h.in.nz - z0);
+                    C->h_tiles.push_back(t);
+                }
+            I.ntiles = (int)C->h_tiles.size() - I.tile0;
+            continue;
+        }
         for (int z0 = 0; z0 < h.in.nz; z0 += h.tz)
             for (int y0 = 0; y0 < h.in.ny; y0 += s.ty)
                 for (int x0 = 0; x0 < h.in.nx; x0 += s.tx) {
@@ -379,20 +436,25 @@ void build_tiles(sllg_ctx* C, LevelHost& h)
 void default_stream_shape(const sllg_ctx* C, LevelHost& h)
 {
     int best = -1;
-    for (int i = 0; i < kNumShapes; ++i)
-        if (kShapes[i].tx >= h.in.nx && kShapes[i].ty >= h.in.ny) {
-            if (best < 0 || kShapes[i].tx * kShapes[i].ty < kShapes[best].tx * kShapes[best].ty ||
-                (kShapes[i].tx * kShapes[i].ty == kShapes[best].tx * kShapes[best].ty &&
-                 kShapes[i].pz > kShapes[best].pz))
-                best = i;
+    // full-width rows kernel: the fewest threads that hold a whole plane, else 1024 x 2
+    for (int i = 0; i < kNumShapes; ++i) {
+        const Shape& s = kShapes[i];
+        if (s.kind != 1 || !shape_fits(h.in, s)) continue;
+        if ((s.tx / h.in.nx) * s.ty >= h.in.ny) {
+            if (best < 0 || s.tx * s.ty < kShapes[best].tx * kShapes[best].ty) best = i;
         }
+    }
+    if (best < 0)
+        for (int i = 0; i < kNumShapes; ++i)
+            if (kShapes[i].kind == 1 && kShapes[i].tx == 512 && kShapes[i].ty == 2 && shape_fits(h.in, kShapes[i]))
+                best = i;
     if (best < 0) best = 0;
     h.shape = best;
     const Shape s = kShapes[best];
-    const int64_t xy = ceil_div(h.in.nx, s.tx) * ceil_div(h.in.ny, s.ty) * h.ninst;
+    const int64_t xy = tiles_for(h.in, s, h.in.nz) * h.ninst;
     int tz = 64;
-    while (tz > 1 && xy * ceil_div(h.in.nz, tz) < 4LL * C->num_cus) tz /= 2;
-    h.tz = std::max(tz, s.pz > 1 ? std::min(s.pz, h.in.nz) : 1);
+    while (tz > 1 && xy * ceil_div(h.in.nz, tz) < 2LL * C->num_cus) tz /= 2;
+    h.tz = s.kind == 0 ? std::max(tz, std::min(s.pz, h.in.nz)) : tz;
 }
 
 // Group instances of resident levels with equal sweep length.
@@ -562,15 +624,38 @@ hipError_t launch_stream_t(sllg_ctx* C, int level)
     const LevelHost& h = C->lv[level];
     hipLaunchKernelGGL((k_stream<TX, TY, PZ>), dim3(h.ntiles), dim3(TX * TY * PZ), 0, C->stream,
                        C->d_tiles, C->d_insts, C->d_levels, C->d_buf0, C->d_buf1, C->d_axes,
-                       C->d_steps, level, 1, h.tile0, C->d_partials, C->d_inst_cnt,
+                       C->d_steps, h.tile0, (int)C->lay.max_tiles, C->d_partials, C->d_inst_cnt,
                        C->d_launch_cnt + level, C->d_records, C->d_accs, C->d_ckpt, C->ckpt_every,
                        C->d_status);
+    return hipGetLastError();
+}
+
+template <int NT, int K>
+hipError_t launch_rows_t(sllg_ctx* C, int level)
+{
+    const LevelHost& h = C->lv[level];
+    hipLaunchKernelGGL((k_rows<NT, K>), dim3(h.ntiles), dim3(NT), 0, C->stream, C->d_tiles, C->d_insts,
+                       C->d_levels, C->d_buf0, C->d_buf1, C->d_axes, C->d_steps, h.tile0,
+                       (int)C->lay.max_tiles, C->d_partials, C->d_inst_cnt, C->d_launch_cnt + level,
+                       C->d_records, C->d_accs, C->d_ckpt, C->ckpt_every, C->d_status);
     return hipGetLastError();
 }
 
 hipError_t dispatch_stream(sllg_ctx* C, int level)
 {
     const Shape s = kShapes[C->lv[level].shape];
+    if (s.kind == 1) {
+        switch (s.tx * 10 + s.ty) {
+        case 1921: return launch_rows_t<192, 1>(C, level);
+        case 2561: return launch_rows_t<256, 1>(C, level);
+        case 2562: return launch_rows_t<256, 2>(C, level);
+        case 5121: return launch_rows_t<512, 1>(C, level);
+        case 5122: return launch_rows_t<512, 2>(C, level);
+        case 10241: return launch_rows_t<1024, 1>(C, level);
+        case 2564: return launch_rows_t<256, 4>(C, level);
+        default: return hipErrorInvalidValue;
+        }
+    }
     const int key = s.tx * 10000 + s.ty * 10 + s.pz;
     switch (key) {
     case 640081: return launch_stream_t<64, 8, 1>(C, level);
@@ -596,30 +681,84 @@ hipEvent_t next_event(sllg_ctx* C)
     return C->ev_pool[C->ev_used++];
 }
 
+constexpr int kGraphSteps = 128;
+
+// Fold the last streamed step of every instance of a level into its loop.
+hipError_t flush_level(sllg_ctx* C, int level)
+{
+    const LevelHost& h = C->lv[level];
+    hipLaunchKernelGGL(k_flush, dim3((unsigned)h.ninst), dim3(64), 0, C->stream, C->d_insts, h.inst0, C->d_levels,
+                       C->d_steps, C->d_partials, (int)C->lay.max_tiles, C->d_inst_cnt, C->d_accs, C->d_records,
+                       C->d_status);
+    return hipGetLastError();
+}
+
+// Graph of kGraphSteps consecutive stream launches of one level.
+int stream_graph(sllg_ctx* C, int level, hipGraphExec_t* out)
+{
+    auto it = C->graphs.find(level);
+    if (it != C->graphs.end()) {
+        *out = it->second;
+        return SLLG_OK;
+    }
+    if (!C->cap_stream) HIP_OK(hipStreamCreateWithFlags(&C->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = C->stream;
+    C->stream = C->cap_stream;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(C->cap_stream, hipStreamCaptureModeThreadLocal);
+    for (int i = 0; i < kGraphSteps && e == hipSuccess; ++i) e = dispatch_stream(C, level);
+    hipError_t e2 = hipStreamEndCapture(C->cap_stream, &g);
+    C->stream = user;
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(SLLG_E_HIP, "graph capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(SLLG_E_HIP, "graph instantiate: %s", hipGetErrorString(e));
+    C->graphs[level] = x;
+    *out = x;
+    return SLLG_OK;
+}
+
 // Run up to nsteps of every unfinished level.
 int run_steps(sllg_ctx* C, int64_t nsteps)
 {
     if (nsteps <= 0) return SLLG_OK;
-    // stream levels: one launch per step (optionally replayed from a graph)
+    // stream levels: one launch per step, replayed from a HIP graph in blocks
     for (int l = 0; l < (int)C->lv.size(); ++l) {
         LevelHost& h = C->lv[l];
         if (h.plan != kPlanStream) continue;
-        const int64_t k = std::min(nsteps, h.n_steps - h.step);
-        for (int64_t s = 0; s < k; ++s) {
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (C->timing) {
-                e0 = next_event(C);
-                e1 = next_event(C);
+        int64_t k = std::min(nsteps, h.n_steps - h.step);
+        h.step += k;
+        while (k > 0) {
+            if (C->timing > 0 && (C->launch_counter % C->timing) == 0) {
+                hipEvent_t e0 = next_event(C), e1 = next_event(C);
                 if (!e0 || !e1) return fail(SLLG_E_HIP, "event pool");
                 HIP_OK(hipEventRecord(e0, C->stream));
-            }
-            HIP_OK(dispatch_stream(C, l));
-            if (C->timing) {
+                HIP_OK(dispatch_stream(C, l));
                 HIP_OK(hipEventRecord(e1, C->stream));
                 C->timed_cells = h.ncell * h.ninst;
+                C->launch_counter++;
+                k--;
+                continue;
             }
+            int64_t until_timed = C->timing > 0 ? C->timing - (C->launch_counter % C->timing) : k;
+            if (C->use_graph && k >= kGraphSteps && until_timed >= kGraphSteps) {
+                hipGraphExec_t g = nullptr;
+                int rc = stream_graph(C, l, &g);
+                if (rc) return rc;
+                HIP_OK(hipGraphLaunch(g, C->stream));
+                C->launch_counter += kGraphSteps;
+                k -= kGraphSteps;
+                continue;
+            }
+            HIP_OK(dispatch_stream(C, l));
+            C->launch_counter++;
+            k--;
         }
-        h.step += k;
+        HIP_OK(flush_level(C, l));
     }
     // resident sets: launches of at most 32768 steps
     for (const auto& rs : C->res_sets) {
@@ -628,7 +767,7 @@ int run_steps(sllg_ctx* C, int64_t nsteps)
         while (k > 0) {
             const int64_t ns = std::min<int64_t>(k, 32768);
             hipEvent_t e0 = nullptr, e1 = nullptr;
-            const bool time_this = C->timing && !std::any_of(C->lv.begin(), C->lv.end(), [](const LevelHost& x) {
+            const bool time_this = C->timing > 0 && !std::any_of(C->lv.begin(), C->lv.end(), [](const LevelHost& x) {
                 return x.plan == kPlanStream;
             });
             if (time_this) {
@@ -682,16 +821,35 @@ int tune_stream(sllg_ctx* C, int level)
         return SLLG_OK;
     }
     default_stream_shape(C, h);
+    // SLLG_STREAM_SHAPE="shape,tz" pins the tile shape (experiments)
+    if (const char* f = getenv("SLLG_STREAM_SHAPE")) {
+        int sh = -1, tz = -1;
+        if (sscanf(f, "%d,%d", &sh, &tz) == 2 && sh >= 0 && sh < kNumShapes && tz >= 1 &&
+            shape_fits(h.in, kShapes[sh]) && tiles_for(h.in, kShapes[sh], tz) * h.ninst <= C->lay.max_tiles) {
+            h.shape = sh;
+            h.tz = tz;
+            g_tuned[key] = {sh, tz};
+            return SLLG_OK;
+        }
+    }
     std::vector<std::pair<int, int>> cands;
     for (int s = 0; s < kNumShapes; ++s) {
         const Shape& S = kShapes[s];
-        // keep shapes whose window is not mostly idle
-        const double use = (double)std::min(S.tx, h.in.nx) * std::min(S.ty, h.in.ny) / (S.tx * S.ty);
+        if (!shape_fits(h.in, S)) continue;
+        // keep shapes whose threads are mostly busy
+        double use;
+        if (S.kind == 0) {
+            use = (double)std::min(S.tx, h.in.nx) * std::min(S.ty, h.in.ny) / (S.tx * S.ty);
+        } else {
+            const int TR = S.tx / h.in.nx;
+            use = (double)(TR * h.in.nx) / S.tx * std::min(1.0, (double)h.in.ny / (TR * S.ty));
+        }
         if (use < 0.5) continue;
         for (int tz : kTzChoices) {
             if (tz < S.pz || tz > h.in.nz * 2) continue;
             const int64_t nt = tiles_for(h.in, S, tz) * h.ninst;
-            if (nt < C->num_cus / 2 && tz > 1) continue;
+            if (nt == 0) continue;
+            if (nt < C->num_cus / 4 && tz > 1) continue;
             if (nt > C->lay.max_tiles) continue;
             cands.push_back({s, tz});
         }
@@ -719,11 +877,16 @@ int tune_stream(sllg_ctx* C, int level)
         HIP_OK(hipEventSynchronize(e1));
         float ms = 0;
         HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+        if (getenv("SLLG_TUNE_VERBOSE"))
+            fprintf(stderr, "tune level %d: shape %d (%d,%d,%d,%d) tz %d tiles %d: %.2f us/step\n", level,
+                    c.first, kShapes[c.first].kind, kShapes[c.first].tx, kShapes[c.first].ty,
+                    kShapes[c.first].pz, c.second, h.ntiles, 1000.0 * ms / reps);
         if (ms < best_t) {
             best_t = ms;
             best = c;
         }
         HIP_OK(hipMemsetAsync(C->d_steps, 0, sizeof(int64_t) * C->lv.size(), C->stream));
+        HIP_OK(hipMemsetAsync(C->d_inst_cnt, 0, sizeof(uint32_t) * C->lay.ninst_total, C->stream));
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -774,10 +937,10 @@ double wave_host(const LevelHost& h, int wave, int64_t n)
     const int64_t N = h.n_period;
     const int64_t k = n % N;
     if (wave == 0) {
-        const double s = (double)k / (double)N;
+        const double s = (double)k * (1.0 / (double)N);
         return (2 * k <= N) ? 1.0 - 4.0 * s : 4.0 * s - 3.0;
     }
-    if (wave == 1) return std::cos(2.0 * kPi * (double)k / (double)N);
+    if (wave == 1) return std::cos(2.0 * kPi * ((double)k * (1.0 / (double)N)));
     return 1.0;
 }
 
@@ -891,6 +1054,7 @@ int sllg_init(const sllg_material* mat, const sllg_level* levels, int32_t n_leve
         C->max_lds = (int)std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
         C->num_cus = prop.multiProcessorCount;
     }
+    C->use_graph = !(getenv("SLLG_GRAPH") && getenv("SLLG_GRAPH")[0] == '0');
     C->h_levels.resize(n_levels);
     for (int i = 0; i < n_levels; ++i) {
         LevelHost& h = C->lv[i];
@@ -1064,7 +1228,7 @@ int sllg_level_params(const sllg_ctx* C, int32_t level, double out[16])
     const LevelHost& h = C->lv[level];
     const double v[16] = {h.zeta, h.A, h.K, h.Ms, h.a, h.c_ex, h.hk, h.gamma1, h.alpha, h.sigma, h.dt,
                           h.hscale, h.cM, (double)h.n_steps, h.hz_amp,
-                          (double)(h.plan * 100 + (h.plan == kPlanStream ? h.shape : 0))};
+                          (double)(h.plan * 100000 + (h.plan == kPlanStream ? h.shape * 1000 + h.tz : 0))};
     std::memcpy(out, v, sizeof(v));
     return SLLG_OK;
 }
@@ -1192,8 +1356,9 @@ int sllg_get_axes(sllg_ctx* C, int32_t level, float* host_u)
 int sllg_set_timing(sllg_ctx* C, int32_t on)
 {
     if (!C) return fail(SLLG_E_INVAL, "null context");
-    C->timing = on != 0;
+    C->timing = on > 0 ? on : 0;
     C->ev_used = 0;
+    C->launch_counter = 0;
     return SLLG_OK;
 }
 
@@ -1217,16 +1382,92 @@ int sllg_kernel_time(sllg_ctx* C, double* mean_ms, int64_t* launches, int64_t* c
 
 int sllg_grad(sllg_ctx* C, int32_t level, double g_area[4], double g_hc[4])
 {
-    (void)g_area;
-    (void)g_hc;
-    if (!C || level < 0 || level >= (int)C->lv.size()) return fail(SLLG_E_INVAL, "bad level");
-    return fail(SLLG_E_STATE, "adjoint not built yet");
+    if (!C || level < 0 || level >= (int)C->lv.size() || !g_area || !g_hc)
+        return fail(SLLG_E_INVAL, "bad arguments");
+    const LevelHost& h = C->lv[level];
+    if (C->ckpt_every <= 0 || !C->d_ckpt)
+        return fail(SLLG_E_STATE, "sllg_grad needs checkpoints: pass ckpt_every > 0 to sllg_init");
+    if (h.in.record_every != 1) return fail(SLLG_E_STATE, "sllg_grad needs record_every == 1");
+    if (h.step != h.n_steps) return fail(SLLG_E_STATE, "run the whole sweep before sllg_grad");
+    if (h.ncell > 1024) return fail(SLLG_E_INVAL, "the adjoint holds at most 1024 cells per realization");
+    int rc = check_status(C);
+    if (rc) return rc;
+    const int64_t NS = h.n_steps, R = h.ninst;
+    // ensemble-mean loop and the loss weights dL/dmbar_n of one realization
+    std::vector<double> rec((size_t)(R * (NS + 1)));
+    for (int r = 0; r < R; ++r)
+        HIP_OK(hipMemcpyAsync(rec.data() + (size_t)r * (NS + 1), C->d_records + C->h_insts[h.inst0 + r].rec_off,
+                              sizeof(double) * (NS + 1), hipMemcpyDeviceToHost, C->stream));
+    HIP_OK(hipStreamSynchronize(C->stream));
+    std::vector<double> H(NS + 1), m(NS + 1, 0.0), w(2 * (NS + 1), 0.0);
+    const double hz_oe = h.hz_amp / kOe;
+    for (int64_t k = 0; k <= NS; ++k) H[k] = hz_oe * wave_host(h, C->mat.wave, k);
+    for (int r = 0; r < R; ++r)
+        for (int64_t k = 0; k <= NS; ++k) m[k] += rec[(size_t)r * (NS + 1) + k];
+    for (int64_t k = 0; k <= NS; ++k) m[k] /= (double)R;
+    for (int64_t k = 0; k < NS; ++k) {   // area: S = -sum (m_k + m_{k+1})/2 (H_{k+1} - H_k)
+        const double dH = H[k + 1] - H[k];
+        w[k] -= 0.5 * dH;
+        w[k + 1] -= 0.5 * dH;
+    }
+    const Stats st = analyse(H, m);
+    const bool hc_ok = st.kd >= 0 && st.ka >= 0;
+    if (hc_ok) {   // Hc = (H*_asc - H*_desc)/2, H* = H_k - m_k dH/(m_{k+1} - m_k)
+        const int ks[2] = {st.kd, st.ka};
+        const double sg[2] = {-0.5, 0.5};
+        for (int b = 0; b < 2; ++b) {
+            const int k = ks[b];
+            const double dH = H[k + 1] - H[k], D = m[k + 1] - m[k];
+            w[(NS + 1) + k] += sg[b] * (-dH * m[k + 1] / (D * D));
+            w[(NS + 1) + k + 1] += sg[b] * (dH * m[k] / (D * D));
+        }
+    }
+    for (double& x : w) x /= (double)R;
+    HIP_OK(hipMemcpyAsync(C->d_weights, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice, C->stream));
+    const int nt = h.ncell <= 64 ? 64 : h.ncell <= 128 ? 128 : h.ncell <= 192 ? 192 : h.ncell <= 256 ? 256
+                 : h.ncell <= 512 ? 512 : 1024;
+#define SLLG_ADJ(NT)                                                                                          \
+    hipLaunchKernelGGL(k_adjoint<NT>, dim3((unsigned)R), dim3(NT), 0, C->stream, C->d_insts, h.inst0,         \
+                       C->d_levels, C->d_axes, C->d_ckpt, C->ckpt_every, C->d_tape, C->d_weights, C->d_grads)
+    switch (nt) {
+    case 64: SLLG_ADJ(64); break;
+    case 128: SLLG_ADJ(128); break;
+    case 192: SLLG_ADJ(192); break;
+    case 256: SLLG_ADJ(256); break;
+    case 512: SLLG_ADJ(512); break;
+    default: SLLG_ADJ(1024); break;
+    }
+#undef SLLG_ADJ
+    HIP_OK(hipGetLastError());
+    std::vector<double> gr((size_t)(10 * R));
+    HIP_OK(hipMemcpyAsync(gr.data(), C->d_grads + 10 * h.inst0, sizeof(double) * gr.size(), hipMemcpyDeviceToHost,
+                          C->stream));
+    HIP_OK(hipStreamSynchronize(C->stream));
+    double g[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
+    for (int r = 0; r < R; ++r)
+        for (int l = 0; l < 2; ++l)
+            for (int k = 0; k < 5; ++k) g[l][k] += gr[(size_t)r * 10 + l * 5 + k];
+    // chain rule from (c_ex, H_K, gamma1, alpha|gamma1, sigma) to (K, A, alpha, ms_scale)
+    const double al = h.alpha, Ms = h.Ms;
+    for (int l = 0; l < 2; ++l) {
+        double* out = l == 0 ? g_area : g_hc;
+        const double gc = g[l][0], gk = g[l][1], gg = g[l][2], ga = g[l][3], gs = g[l][4];
+        out[0] = gk * 2.0 / (kMu0 * Ms);                              // dH_K/dK
+        out[1] = gc * 2.0 / (kMu0 * Ms * h.a * h.a);                  // dc_ex/dA
+        out[2] = ga + gg * (-2.0 * al * kGamma0 / ((1.0 + al * al) * (1.0 + al * al))) +
+                 (al > 0 ? gs * h.sigma / (2.0 * al) : 0.0);           // gamma1(alpha), sigma(alpha)
+        out[3] = C->mat.Ms0 * (-gc * h.c_ex / Ms - gk * h.hk / Ms - gs * h.sigma / (2.0 * Ms));
+    }
+    if (!hc_ok)
+        for (int k = 0; k < 4; ++k) g_hc[k] = NAN;
+    return SLLG_OK;
 }
 
 void sllg_free(sllg_ctx* C)
 {
     if (!C) return;
     for (hipEvent_t e : C->ev_pool) (void)hipEventDestroy(e);
+    if (C->cap_stream) (void)hipStreamDestroy(C->cap_stream);
     for (const auto& g : C->graphs) (void)hipGraphExecDestroy(g.second);
     delete C;
 }

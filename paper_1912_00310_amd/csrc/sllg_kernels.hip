@@ -261,8 +261,8 @@ template <int TX, int TY, int PZ>
 __global__ __launch_bounds__(TX* TY* PZ) void k_stream(
     const TileDev* __restrict__ tiles, const InstDev* __restrict__ insts,
     const LevelDev* __restrict__ levels, float* __restrict__ buf0, float* __restrict__ buf1,
-    const float* __restrict__ axes, int64_t* __restrict__ steps, int lev0, int nlev, int tile_base,
-    double* __restrict__ partials, uint32_t* __restrict__ inst_cnt, uint32_t* __restrict__ launch_cnt,
+    const float* __restrict__ axes, int64_t* __restrict__ steps, int tile_base, int ptiles,
+    double* __restrict__ partials, uint32_t* __restrict__ pend, uint32_t* __restrict__ launch_cnt,
     double* __restrict__ records, AccDev* __restrict__ accs, float* __restrict__ ckpt, int ckpt_every,
     int* __restrict__ status)
 {
@@ -275,7 +275,6 @@ __global__ __launch_bounds__(TX* TY* PZ) void k_stream(
     __shared__ float Mp[NS][3][R1];
     __shared__ float QH[NQ][6][TXY];
     __shared__ double red[NT / 64];
-    __shared__ int s_last;
 
     const int tid = threadIdx.x;
     const int tile = tile_base + static_cast<int>(blockIdx.x);
@@ -283,6 +282,11 @@ __global__ __launch_bounds__(TX* TY* PZ) void k_stream(
     const InstDev I = insts[T.inst];
     const LevelDev L = levels[I.level];
     const int64_t n = steps[I.level];
+    const bool first_tile = tile == I.tile0;
+    if (first_tile && pend[T.inst]) {
+        fold_partials(I, L, n - 1, partials, ptiles, accs, T.inst, records, status);
+        if (tid == 0) pend[T.inst] = 0u;
+    }
 
     if (n < L.n_steps) {
         const float* __restrict__ mi = ((n & 1) ? buf1 : buf0) + I.state_off;
@@ -421,42 +425,24 @@ __global__ __launch_bounds__(TX* TY* PZ) void k_stream(
                 }
             }
         }
-        // block partial of sum m_z (FP32 per wave, FP64 across waves)
-        const float ws = wave_sum(msum);
-        if ((tid & 63) == 0) red[tid >> 6] = static_cast<double>(ws);
-        __syncthreads();
-        if (tid == 0) {
-            double tot = 0.0;
-            for (int w = 0; w < NT / 64; ++w) tot += red[w];
-            __hip_atomic_store(&partials[tile], tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence();
-            const uint32_t prev = atomicAdd(&inst_cnt[T.inst], 1u);
-            s_last = (prev == static_cast<uint32_t>(I.ntiles - 1));
-        }
-        __syncthreads();
-        if (s_last && tid == 0) {
-            __threadfence();
-            double sum = 0.0;
-            for (int t = 0; t < I.ntiles; ++t)
-                sum += __hip_atomic_load(&partials[I.tile0 + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            AccDev a = accs[T.inst];
-            loop_accumulate(a, L, n, sum / static_cast<double>(N), records + I.rec_off);
-            accs[T.inst] = a;
-            if (!isfinite(a.m_prev)) atomicOr(status, 1);
-            inst_cnt[T.inst] = 0u;
-        }
+        const double tot = block_sum<TX * TY * PZ>(msum, red);
+        stream_block_end(tot, n, tile, ptiles, partials, first_tile, pend, T.inst, launch_cnt, steps, I.level,
+                         L.n_steps);
     }
-    // the last workgroup of the launch advances the step counters
-    if (tid == 0) {
-        __threadfence();
-        const uint32_t prev = atomicAdd(launch_cnt, 1u);
-        if (prev == gridDim.x - 1) {
-            __threadfence();
-            for (int l = lev0; l < lev0 + nlev; ++l)
-                if (steps[l] < levels[l].n_steps) steps[l] += 1;
-            *launch_cnt = 0u;
-        }
-    }
+}
+
+// Fold the last pending step of every instance of a stream-plan level.
+__global__ void k_flush(const InstDev* __restrict__ insts, int inst0, const LevelDev* __restrict__ levels,
+                        const int64_t* __restrict__ steps, const double* __restrict__ partials, int ptiles,
+                        uint32_t* __restrict__ pend, AccDev* __restrict__ accs, double* __restrict__ records,
+                        int* __restrict__ status)
+{
+    const int inst = inst0 + static_cast<int>(blockIdx.x);
+    const InstDev I = insts[inst];
+    if (!pend[inst]) return;
+    const LevelDev& L = levels[I.level];
+    fold_partials(I, L, steps[I.level] - 1, partials, ptiles, accs, inst, records, status);
+    if (threadIdx.x == 0) pend[inst] = 0u;
 }
 
 // ---------------------------------------------------------------------------

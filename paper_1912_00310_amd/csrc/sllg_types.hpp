@@ -21,6 +21,7 @@ struct LevelDev {
     double hz_oe;    // the same peak in Oe
     int64_t n_period;        // steps per field cycle
     int64_t n_steps;         // steps per sweep
+    double inv_period;       // 1 / n_period
     int32_t wave;            // 0 triangle, 1 cosine, 2 constant
     int32_t level_tag;       // RNG counter field
     int32_t record_every;
@@ -51,7 +52,8 @@ struct AccDev {
     double m0_d, m0_a;         // loop ordinate where H crosses 0 falling / rising
     int32_t ncross_d, ncross_a;
     int32_t found_d, found_a, found0_d, found0_a;
-    int32_t pad0, pad1;
+    int32_t rec_phase;   // steps since the last recorded point
+    int32_t rec_idx;     // index of the last recorded point
 };
 
 // A tile of the stream plan: an x-y window of one instance and a z range.

@@ -252,8 +252,9 @@ class Sim:
                                                     out.ctypes.data_as(C.POINTER(C.c_float))))
         return out.reshape(3, -1)
 
-    def set_timing(self, on: bool):
-        _check("sllg_set_timing", lib().sllg_set_timing(self.ctx, int(bool(on))))
+    def set_timing(self, every: int):
+        """Bracket every ``every``-th launch of the dominant kernel with events (0: off)."""
+        _check("sllg_set_timing", lib().sllg_set_timing(self.ctx, int(every)))
 
     def kernel_time(self):
         """(mean ms per launch of the dominant kernel, launches, cell-updates per launch)."""

@@ -1,0 +1,185 @@
+"""GPU parity of whole loops and of the loop bookkeeping.
+
+Full-sweep statistics are compared with the FP64 oracle run on the same
+Philox stream: loop area and coercive field within two standard errors of
+the ensemble (the bar for whole finite-temperature loops), the number of
+zero crossings equal, and per-step records of the first steps within the
+trajectory tolerance.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import sllg_workloads as W
+from oracle import gk
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1912_00310_amd as P
+    P.lib()
+    return P
+
+
+def oracle_ensemble(orc, wl, level=0):
+    lv = gk.compile_level(wl["material"], wl["levels"][level], level)
+    L = wl["levels"][level]
+    seeds = [L["seed_base"] + r for r in range(L["n_real"])]
+    mbar, _ = orc.run_batch(lv, seeds, lv["n_steps"], u=orc.make_axes(lv))
+    H = orc.field_schedule_Oe(lv)
+    return lv, H, mbar, orc.ensemble_stats(lv, H, mbar)
+
+
+def two_sigma(a, b, se_a, se_b):
+    s = math.sqrt(se_a ** 2 + se_b ** 2)
+    return abs(a - b) <= 2 * s, abs(a - b), s
+
+
+def switching_workload(n_real=16):
+    """b = 8 rod, alpha = 1, 50 fs steps, 500 Oe/ns: loops that reverse."""
+    wl = W.workload("rod_b4_single")
+    wl["material"]["sweep_Oe_per_ns"] = 500.0
+    wl["levels"][0].update(b=8, nx=1, ny=3, nz=7, alpha=1.0, dt_s=50e-15, n_real=n_real)
+    return wl
+
+
+def test_rod_b4_full_sweep_16_realizations(P, orc):
+    # the 2x6x14 b=4 rod at 2e4 Oe/ns does not reverse: no crossing on either side
+    wl = W.workload("rod_b4_single")
+    wl["levels"][0]["n_real"] = 16
+    lv, H, mbar, ref = oracle_ensemble(orc, wl)
+    sim = P.Sim(wl["material"], wl["levels"])
+    sim.run_sweep()
+    Hg, mg, st = sim.loop(0, -1)
+    assert np.allclose(Hg, H, rtol=0, atol=1e-9)
+    ok, d, s = two_sigma(st["S_sim"], ref["S_sim"], st["S_se"], ref["S_se"])
+    assert ok, (st["S_sim"], ref["S_sim"], s)
+    # same stream: the loops themselves stay close (FP32 vs FP64)
+    assert np.abs(mg - mbar.mean(axis=0)).max() < 5e-3
+    assert abs(st["S_sim"] - ref["S_sim"]) < 0.05 * abs(ref["S_sim"]) + 0.5
+    assert math.isnan(st["Hc_sim"]) == math.isnan(ref["Hc"])
+    assert st["n_cross_desc"] == ref["mean_loop"]["n_cross_desc"]
+    assert st["Mr_sim"] == pytest.approx(ref["Mr"], abs=5e-3)
+    # physical units: H/zeta and the Eq. (13) factor
+    assert st["S_phys"] == pytest.approx(st["S_sim"] * lv["cM"] / lv["hscale"], rel=1e-12)
+    sim.close()
+
+
+def test_switching_loop_hc_and_area_within_two_sigma(P, orc):
+    wl = switching_workload(16)
+    lv, H, mbar, ref = oracle_ensemble(orc, wl)
+    assert not math.isnan(ref["Hc"])
+    sim = P.Sim(wl["material"], wl["levels"])
+    sim.run_sweep()
+    _, mg, st = sim.loop(0, -1)
+    ok, d, s = two_sigma(st["Hc_sim"], ref["Hc"], st["Hc_se"], ref["Hc_se"])
+    assert ok, ("Hc", st["Hc_sim"], ref["Hc"], s)
+    ok, d, s = two_sigma(st["S_sim"], ref["S_sim"], st["S_se"], ref["S_se"])
+    assert ok, ("S", st["S_sim"], ref["S_sim"], s)
+    # the first 1000 steps of the mean loop agree to the trajectory tolerance
+    assert np.abs(mg[:1001] - mbar.mean(axis=0)[:1001]).max() < 1e-5
+    sim.close()
+
+
+def test_per_realization_accumulators_match_records(P):
+    # the online area (every step) equals the trapezoid over the full record
+    wl = switching_workload(4)
+    sim = P.Sim(wl["material"], wl["levels"])
+    sim.run_sweep()
+    for r in range(4):
+        H, m, st = sim.loop(0, r)
+        S = -np.sum(0.5 * (m[1:] + m[:-1]) * np.diff(H))
+        assert st["S_sim"] == pytest.approx(S, rel=1e-12, abs=1e-9)
+    sim.close()
+
+
+def test_decimated_records(P):
+    wl = switching_workload(2)
+    full = P.Sim(wl["material"], wl["levels"])
+    full.run_steps(5003)
+    wl2 = switching_workload(2)
+    wl2["levels"][0]["record_every"] = 10
+    dec = P.Sim(wl2["material"], wl2["levels"])
+    dec.run_steps(5003)
+    H1, m1, s1 = full.loop(0, 1)
+    H2, m2, s2 = dec.loop(0, 1)
+    assert len(m2) == 5003 // 10 + 1
+    assert np.array_equal(m2, m1[::10][:len(m2)])
+    assert np.array_equal(H2, H1[::10][:len(m2)])
+    assert s2["S_sim"] == s1["S_sim"]          # area uses every step either way
+    full.close()
+    dec.close()
+
+
+def test_plans_agree_on_full_loops(P):
+    wl = switching_workload(3)
+    res = []
+    for plan in (P.PLAN_RESIDENT, P.PLAN_STREAM):
+        sim = P.Sim(wl["material"], wl["levels"])
+        sim.set_plan(0, plan)
+        sim.run_sweep()
+        res.append((sim.get_state(0, 2), sim.loop(0, -1)))
+        sim.close()
+    assert np.array_equal(res[0][0], res[1][0])
+    # the ordinates differ only in how the FP32 partial sums of m_z are grouped
+    # (64-lane waves vs tiles): at most a few FP32 ulps of the mean
+    assert np.abs(res[0][1][1] - res[1][1][1]).max() < 1e-6
+    assert res[0][1][2]["Hc_sim"] == pytest.approx(res[1][1][2]["Hc_sim"], rel=1e-5)
+
+
+def test_multilevel_batch_each_level_matches_oracle(P, orc):
+    # four coarse-graining levels in one context (b = 1 streamed, b = 2, 4, 8
+    # resident in packed workgroups); a short window against the oracle
+    wl = W.workload("multilevel_ens256")
+    for lvd in wl["levels"]:
+        lvd["n_real"] = 3
+        lvd["record_every"] = 1
+    sim = P.Sim(wl["material"], wl["levels"])
+    nst = 300
+    sim.run_steps(nst)
+    for l, lvd in enumerate(wl["levels"]):
+        lv = gk.compile_level(wl["material"], lvd, l)
+        assert sim.level_params(l)["alpha"] == pytest.approx(400.0)
+        N = lv["nx"] * lv["ny"] * lv["nz"]
+        for r in (0, 2):
+            m_ref, mb = orc.run(lv, lvd["seed_base"] + r, 0, nst, np.tile([0.0, 0.0, 1.0], (N, 1)))
+            d = np.abs(sim.get_state(l, r).T - m_ref).max()
+            assert d < 1e-5, (l, r, d)
+            _, mg, _ = sim.loop(l, r)
+            assert np.abs(mg - mb).max() < 2e-6
+    sim.close()
+
+
+def test_state_roundtrip_and_reset(P):
+    wl = W.workload("rod_b4_single")
+    sim = P.Sim(wl["material"], wl["levels"])
+    sim.run_steps(100)
+    m = sim.get_state(0, 0)
+    sim.set_state(m, 0, 0)
+    assert np.array_equal(sim.get_state(0, 0), m)
+    sim.reset()
+    assert sim.step(0) == 0
+    m0 = sim.get_state(0, 0)
+    assert np.array_equal(m0[2], np.ones_like(m0[2])) and not m0[:2].any()
+    sim.close()
+
+
+def test_numeric_blowup_is_reported(P):
+    # an absurd temperature overflows the FP32 thermal field; the library says so
+    wl = W.workload("rod_b4_single")
+    wl["material"]["T_K"] = 1e60
+    sim = P.Sim(wl["material"], wl["levels"])
+    sim.run_steps(200)
+    m = sim.get_state(0, 0)
+    if np.all(np.isfinite(m)):
+        pytest.skip("integration stayed finite at this step")
+    with pytest.raises(P.SllgError) as e:
+        sim.loop(0, 0)
+    assert e.value.code == -6
+    sim.close()
