@@ -111,8 +111,9 @@ def main():
     for _ in range(warmup):
         one_step()
     torch.cuda.synchronize()
-    # time every 64th dominant-kernel launch with events on the library's stream
-    sim.set_timing(64 if window >= 10000 else 1)
+    # HIP events on the library's stream around the dominant kernel's launch
+    # units (graph replays of 128 streamed steps, or resident launches)
+    sim.set_timing(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -155,11 +156,13 @@ def main():
         cpu = cpu_baseline(wl, a.cpu_seconds)
 
     if a.copy_probe:
-        n = 1 << 28   # 1 GiB of float32 read and written
-        x = torch.empty(n, dtype=torch.float32, device="cuda")
+        # a plain elementwise copy of known size (1 GiB read, 1 GiB written)
+        # whose FETCH_SIZE / WRITE_SIZE calibrate the counters
+        n = 1 << 28
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
         for _ in range(3):
-            y.copy_(x)
+            torch.add(x, 0.0, out=y)
         torch.cuda.synchronize()
 
     out = {

@@ -157,7 +157,7 @@ void sllg_free(sllg_ctx* ctx);
 
 /* Compiled constants of a level: out[0..15] = zeta, A, K, Ms, a, c_ex, hk,
  * gamma1, alpha, sigma, dt, hscale, cM, n_steps, hz_amp (A/m) and the plan
- * code 100000*plan + 1000*tile shape + z planes per tile (stream plan). */
+ * code 100000*plan + 1000*kernel shape + z planes per tile or slab. */
 int sllg_level_params(const sllg_ctx* ctx, int32_t level, double out[16]);
 
 /* Current step index of a level. */
@@ -172,9 +172,13 @@ int sllg_get_state(sllg_ctx* ctx, int32_t level, int32_t real, float* host_m);
 int sllg_set_state(sllg_ctx* ctx, int32_t level, int32_t real, const float* host_m);
 
 /* Execution plan of a level: 0 = automatic, 1 = LDS-resident persistent
- * kernel, 2 = one fused launch per step over tiles.  Changing the plan is
- * allowed between runs.  Returns SLLG_E_INVAL if the plan cannot hold the
- * level. */
+ * kernel, 2 = one fused launch per step over tiles, 3 = persistent
+ * cooperative launch in which every workgroup owns a z-slab of one
+ * realization for up to 1024 steps and trades boundary planes with its two
+ * neighbours through device memory each step.  All plans give bit-identical
+ * states.  Changing the plan is allowed between runs.  Returns SLLG_E_INVAL
+ * if the plan cannot hold the level (plan 3: more slabs than can be
+ * co-resident, or a slab thicker than the workgroup's LDS holds). */
 int sllg_set_plan(sllg_ctx* ctx, int32_t level, int32_t plan);
 
 /* Device Philox4x32-10 of the thermal-noise stream: for k < n, the four raw
@@ -191,10 +195,13 @@ int sllg_get_axes(sllg_ctx* ctx, int32_t level, float* host_u);
 
 /* Timing of the dominant kernel (the streamed step kernel if a level uses
  * it, else the resident kernel).  sllg_set_timing(ctx, k) with k > 0 brackets
- * every k-th launch with HIP events on the context stream (k = 0 switches it
- * off).  sllg_kernel_time returns the mean duration of the timed launches in
- * milliseconds, how many were timed, and the cell-updates one timed launch
- * performs; it synchronises the stream and restarts the count. */
+ * every k-th launch unit (one launch, or one replay of a graph of streamed
+ * launches) with HIP events on the context stream; k = 0 switches it off.
+ * sllg_kernel_time returns the mean time per kernel launch over the timed
+ * units in milliseconds, the number of launches covered, and the
+ * cell-updates one launch performs; a launch of the slab plan (3) counts as
+ * one launch per step it covers.  It synchronises the stream and restarts
+ * the count. */
 int sllg_set_timing(sllg_ctx* ctx, int32_t every);
 int sllg_kernel_time(sllg_ctx* ctx, double* mean_ms, int64_t* launches, int64_t* cells_per_launch);
 

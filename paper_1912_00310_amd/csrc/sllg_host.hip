@@ -25,6 +25,7 @@
 #include "sllg_kernels.hip"
 #include "sllg_rows.hip"
 #include "sllg_adjoint.hip"
+#include "sllg_slab.hip"
 
 using namespace sllg;
 
@@ -58,7 +59,8 @@ constexpr double kGammaE = 1.76e11;
 constexpr double kGamma0 = kMu0 * kGammaE;
 constexpr double kOe = 1000.0 / (4.0 * kPi);   // A/m per Oe
 
-constexpr int kPlanAuto = 0, kPlanResident = 1, kPlanStream = 2;
+constexpr int kPlanAuto = 0, kPlanResident = 1, kPlanStream = 2, kPlanSlab = 3;
+constexpr int kSlabChunk = 1024;   // steps per slab-plan launch (partials buffer depth)
 
 // Compiled FP64 constants of one level.
 struct LevelHost {
@@ -74,8 +76,22 @@ struct LevelHost {
     int shape;            // index into kShapes
     int tz;
     int tile0, ntiles;
+    // slab plan
+    int slab_kernel;      // index into kSlabKernels
+    int slab_tz;
+    int slab0, nslab;     // slab table range
+    int64_t xch_off;      // float offset of the level's exchange buffer
+    int64_t flags_step;   // step the slab flags currently hold (-1: unknown)
     int64_t step;         // host view of the step index
 };
+
+struct SlabKernel {
+    int nt, k;
+};
+const SlabKernel kSlabKernels[] = {{192, 4}, {384, 2}, {384, 3}, {576, 2}, {768, 1}, {768, 2}, {1024, 1}, {1024, 2}};
+constexpr int kNumSlabKernels = sizeof(kSlabKernels) / sizeof(kSlabKernels[0]);
+
+bool slab_eligible(const sllg_level& L) { return L.nx * L.ny <= 1024 && L.nz >= 4; }
 
 // Stream-plan tile shapes.  kind 0: k_stream<tx, ty, pz> (x-y window with a
 // recomputed ring); kind 1: k_rows<tx = threads, ty = cells per thread>
@@ -98,9 +114,10 @@ const ResidentKernel kResKernels[] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {16, 1}, {
 // Layout of the workspace (byte offsets).
 struct Layout {
     size_t levels, insts, accs, steps, status, inst_cnt, launch_cnt, partials, tiles, groups, slots,
-        chunks, buf0, buf1, axes, records, ckpt, tape, lam, weights, grads, total;
+        chunks, buf0, buf1, axes, records, ckpt, tape, lam, weights, grads, slabs, xch, flags, spart,
+        islab, total;
     int64_t state_floats, axes_floats, rec_doubles, ckpt_floats, tape_floats, lam_floats,
-        max_tiles, max_groups, max_chunks, max_w, ninst_total;
+        max_tiles, max_groups, max_chunks, max_w, ninst_total, max_slabs, xch_floats;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -181,6 +198,13 @@ struct sllg_ctx {
     float* d_lam = nullptr;
     double* d_weights = nullptr;
     double* d_grads = nullptr;
+    SlabDev* d_slabs = nullptr;
+    float* d_xch = nullptr;
+    uint32_t* d_flags = nullptr;
+    double* d_spart = nullptr;
+    int32_t* d_islab = nullptr;   // per instance: first slab (level-relative), then slab count
+    std::vector<SlabDev> h_slabs;
+    std::vector<int32_t> h_islab;
     // host mirrors
     std::vector<LevelDev> h_levels;
     std::vector<InstDev> h_insts;
@@ -197,8 +221,9 @@ struct sllg_ctx {
     std::vector<SlotDev> h_slots;
     std::vector<ChunkDev> h_chunks;
     // timing of the dominant kernel
-    int timing = 0;              // 0 off, k: time every k-th launch of the dominant kernel
-    int64_t launch_counter = 0;
+    int timing = 0;              // 0 off, k: time every k-th launch unit of the dominant kernel
+    int64_t unit_counter = 0;
+    std::vector<int64_t> ev_launches;   // kernel launches inside each timed event pair
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     int64_t timed_cells = 0;
@@ -341,6 +366,11 @@ Layout make_layout(const sllg_material& m, const std::vector<LevelHost>& lv, int
         }
         tiles += max_tiles_for(h.in) * h.in.n_real;
         chunks += ceil_div(h.ncell, 64) * h.in.n_real;
+        if (slab_eligible(h.in)) {
+            const int64_t ns = (int64_t)(h.in.nz / 2) * h.in.n_real;
+            L.max_slabs += ns;
+            L.xch_floats += 2 * ns * 12 * (int64_t)h.in.nx * h.in.ny;
+        }
     }
     (void)m;
     L.ninst_total = ninst;
@@ -381,6 +411,11 @@ Layout make_layout(const sllg_material& m, const std::vector<LevelHost>& lv, int
     L.lam = take(sizeof(float) * lam);
     L.weights = take(sizeof(double) * 2 * maxw);
     L.grads = take(sizeof(double) * 10 * ninst);
+    L.slabs = take(sizeof(SlabDev) * L.max_slabs);
+    L.xch = take(sizeof(float) * L.xch_floats);
+    L.flags = take(sizeof(uint32_t) * L.max_slabs);
+    L.spart = take(sizeof(double) * L.max_slabs * kSlabChunk);
+    L.islab = take(sizeof(int32_t) * 2 * ninst);
     L.total = o;
     return L;
 }
@@ -575,11 +610,59 @@ int upload_tables(sllg_ctx* C)
     return SLLG_OK;
 }
 
+// Slabs of every instance of a slab-plan level: nz split into runs of
+// slab_tz or slab_tz + 1 planes (each at least 2).
+void build_slabs(sllg_ctx* C, LevelHost& h)
+{
+    h.slab0 = (int)C->h_slabs.size();
+    const int nz = h.in.nz;
+    const int tz = std::max(2, h.slab_tz);
+    // ceil(nz / tz) slabs, but never a slab thinner than two planes: every
+    // slab then has at most tz + 1 planes
+    const int nsl = std::max(1, std::min((nz + tz - 1) / tz, nz / 2));
+    const int base = nz / nsl, extra = nz % nsl;
+    for (int r = 0; r < h.ninst; ++r) {
+        const int first = (int)C->h_slabs.size() - h.slab0;
+        C->h_islab[2 * (h.inst0 + r)] = first;
+        C->h_islab[2 * (h.inst0 + r) + 1] = nsl;
+        int z0 = 0;
+        for (int k = 0; k < nsl; ++k) {
+            SlabDev d{};
+            d.inst = h.inst0 + r;
+            d.z0 = z0;
+            d.nzs = base + (k < extra ? 1 : 0);
+            d.prev = k > 0 ? first + k - 1 : -1;
+            d.next = k + 1 < nsl ? first + k + 1 : -1;
+            d.slab0 = first;
+            z0 += d.nzs;
+            C->h_slabs.push_back(d);
+        }
+    }
+    h.nslab = (int)C->h_slabs.size() - h.slab0;
+    h.flags_step = -1;
+}
+
 int replan(sllg_ctx* C)
 {
     C->h_tiles.clear();
-    for (LevelHost& h : C->lv)
+    C->h_slabs.clear();
+    int64_t xo = 0;
+    for (LevelHost& h : C->lv) {
         if (h.plan == kPlanStream) build_tiles(C, h);
+        if (h.plan == kPlanSlab) {
+            build_slabs(C, h);
+            h.xch_off = xo;
+            xo += 2LL * h.nslab * 12 * h.in.nx * h.in.ny;
+        }
+    }
+    if ((int64_t)C->h_slabs.size() > C->lay.max_slabs || xo > C->lay.xch_floats)
+        return fail(SLLG_E_WORKSPACE, "slab tables exceed the reserved workspace");
+    if (!C->h_slabs.empty()) {
+        HIP_OK(hipMemcpyAsync(C->d_slabs, C->h_slabs.data(), sizeof(SlabDev) * C->h_slabs.size(),
+                              hipMemcpyHostToDevice, C->stream));
+        HIP_OK(hipMemcpyAsync(C->d_islab, C->h_islab.data(), sizeof(int32_t) * C->h_islab.size(),
+                              hipMemcpyHostToDevice, C->stream));
+    }
     int rc = build_resident(C);
     if (rc) return rc;
     for (const auto& g : C->graphs) (void)hipGraphExecDestroy(g.second);
@@ -671,6 +754,96 @@ hipError_t dispatch_stream(sllg_ctx* C, int level)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Slab plan
+// ---------------------------------------------------------------------------
+int slab_max_planes(const LevelHost& h)
+{
+    const int tz = std::max(2, h.slab_tz);
+    const int nsl = std::max(1, std::min((h.in.nz + tz - 1) / tz, h.in.nz / 2));
+    return h.in.nz / nsl + (h.in.nz % nsl ? 1 : 0);
+}
+
+size_t slab_lds(const LevelHost& h)
+{
+    return sizeof(float) * (size_t)(2 * slab_max_planes(h) + 6) * 3 * h.in.nx * h.in.ny;
+}
+
+template <int NT, int K>
+hipError_t launch_slab_t(sllg_ctx* C, int level, int64_t n0, int ns, bool check_only, bool* fits)
+{
+    const LevelHost& h = C->lv[level];
+    // every predicted plane (slab + 2 halo planes) must have a thread slot
+    if (slab_max_planes(h) + 2 > K * (NT / (h.in.nx * h.in.ny))) {
+        if (fits) *fits = false;
+        return check_only ? hipSuccess : hipErrorInvalidConfiguration;
+    }
+    const size_t lds = slab_lds(h);
+    const void* fn = reinterpret_cast<const void*>(&k_slab<NT, K>);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    int nb = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, NT, lds);
+    if (e != hipSuccess) return e;
+    if (fits) *fits = (int64_t)nb * C->num_cus >= h.nslab && nb > 0;
+    if (check_only) return hipSuccess;
+    if ((int64_t)nb * C->num_cus < h.nslab) return hipErrorCooperativeLaunchTooLarge;
+    const SlabDev* slabs = C->d_slabs + h.slab0;
+    const InstDev* insts = C->d_insts;
+    const LevelDev* levels = C->d_levels;
+    float* b0 = C->d_buf0;
+    float* b1 = C->d_buf1;
+    const float* axes = C->d_axes;
+    float* xch = C->d_xch + h.xch_off;
+    uint32_t* flags = C->d_flags + h.slab0;
+    double* part = C->d_spart + (int64_t)h.slab0 * kSlabChunk;
+    int pstride = kSlabChunk;
+    float* ckpt = C->d_ckpt;
+    int ck = C->ckpt_every;
+    int* status = C->d_status;
+    void* args[] = {&slabs, &insts, &levels, &b0, &b1, &axes, &xch, &flags, &part, &pstride, &ckpt, &ck,
+                    &n0, &ns, &status};
+    return hipLaunchCooperativeKernel(fn, dim3((unsigned)h.nslab), dim3(NT), args, (unsigned)lds, C->stream);
+}
+
+hipError_t dispatch_slab(sllg_ctx* C, int level, int64_t n0, int ns, bool check_only = false,
+                         bool* fits = nullptr)
+{
+    const SlabKernel k = kSlabKernels[C->lv[level].slab_kernel];
+    switch (k.nt * 10 + k.k) {
+    case 1924: return launch_slab_t<192, 4>(C, level, n0, ns, check_only, fits);
+    case 3842: return launch_slab_t<384, 2>(C, level, n0, ns, check_only, fits);
+    case 3843: return launch_slab_t<384, 3>(C, level, n0, ns, check_only, fits);
+    case 5762: return launch_slab_t<576, 2>(C, level, n0, ns, check_only, fits);
+    case 7681: return launch_slab_t<768, 1>(C, level, n0, ns, check_only, fits);
+    case 7682: return launch_slab_t<768, 2>(C, level, n0, ns, check_only, fits);
+    case 10241: return launch_slab_t<1024, 1>(C, level, n0, ns, check_only, fits);
+    case 10242: return launch_slab_t<1024, 2>(C, level, n0, ns, check_only, fits);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// the flags of a level's slabs must hold the current step before a launch
+int sync_slab_flags(sllg_ctx* C, LevelHost& h)
+{
+    if (h.flags_step == h.step) return SLLG_OK;
+    std::vector<uint32_t> f((size_t)h.nslab, (uint32_t)h.step);
+    HIP_OK(hipMemcpyAsync(C->d_flags + h.slab0, f.data(), sizeof(uint32_t) * f.size(), hipMemcpyHostToDevice,
+                          C->stream));
+    HIP_OK(hipStreamSynchronize(C->stream));
+    h.flags_step = h.step;
+    return SLLG_OK;
+}
+
+hipError_t fold_slabs(sllg_ctx* C, int level, int64_t n0, int ns)
+{
+    const LevelHost& h = C->lv[level];
+    hipLaunchKernelGGL(k_fold_slabs, dim3((unsigned)h.ninst), dim3(64), 0, C->stream, C->d_insts, h.inst0,
+                       C->d_islab + 2 * h.inst0, C->d_levels, C->d_spart + (int64_t)h.slab0 * kSlabChunk,
+                       kSlabChunk, n0, ns, C->d_accs, C->d_records, C->d_status);
+    return hipGetLastError();
+}
+
 hipEvent_t next_event(sllg_ctx* C)
 {
     if (C->ev_used == C->ev_pool.size()) {
@@ -733,32 +906,63 @@ int run_steps(sllg_ctx* C, int64_t nsteps)
         int64_t k = std::min(nsteps, h.n_steps - h.step);
         h.step += k;
         while (k > 0) {
-            if (C->timing > 0 && (C->launch_counter % C->timing) == 0) {
-                hipEvent_t e0 = next_event(C), e1 = next_event(C);
+            // one launch unit: a graph of kGraphSteps launches or one launch;
+            // every C->timing-th unit is bracketed by events
+            const bool graph = C->use_graph && k >= kGraphSteps;
+            const int64_t nl = graph ? kGraphSteps : 1;
+            const bool timed = C->timing > 0 && (C->unit_counter++ % C->timing) == 0;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (timed) {
+                e0 = next_event(C);
+                e1 = next_event(C);
                 if (!e0 || !e1) return fail(SLLG_E_HIP, "event pool");
                 HIP_OK(hipEventRecord(e0, C->stream));
-                HIP_OK(dispatch_stream(C, l));
-                HIP_OK(hipEventRecord(e1, C->stream));
-                C->timed_cells = h.ncell * h.ninst;
-                C->launch_counter++;
-                k--;
-                continue;
             }
-            int64_t until_timed = C->timing > 0 ? C->timing - (C->launch_counter % C->timing) : k;
-            if (C->use_graph && k >= kGraphSteps && until_timed >= kGraphSteps) {
+            if (graph) {
                 hipGraphExec_t g = nullptr;
                 int rc = stream_graph(C, l, &g);
                 if (rc) return rc;
                 HIP_OK(hipGraphLaunch(g, C->stream));
-                C->launch_counter += kGraphSteps;
-                k -= kGraphSteps;
-                continue;
+            } else {
+                HIP_OK(dispatch_stream(C, l));
             }
-            HIP_OK(dispatch_stream(C, l));
-            C->launch_counter++;
-            k--;
+            if (timed) {
+                HIP_OK(hipEventRecord(e1, C->stream));
+                C->ev_launches.push_back(nl);
+                C->timed_cells = h.ncell * h.ninst;
+            }
+            k -= nl;
         }
         HIP_OK(flush_level(C, l));
+    }
+    // slab levels: chunks of kSlabChunk steps, each folded into the loops
+    for (int l = 0; l < (int)C->lv.size(); ++l) {
+        LevelHost& h = C->lv[l];
+        if (h.plan != kPlanSlab) continue;
+        int rc = sync_slab_flags(C, h);
+        if (rc) return rc;
+        int64_t k = std::min(nsteps, h.n_steps - h.step);
+        while (k > 0) {
+            const int ns = (int)std::min<int64_t>(k, kSlabChunk);
+            const bool timed = C->timing > 0 && (C->unit_counter++ % C->timing) == 0;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (timed) {
+                e0 = next_event(C);
+                e1 = next_event(C);
+                if (!e0 || !e1) return fail(SLLG_E_HIP, "event pool");
+                HIP_OK(hipEventRecord(e0, C->stream));
+            }
+            HIP_OK(dispatch_slab(C, l, h.step, ns));
+            if (timed) {
+                HIP_OK(hipEventRecord(e1, C->stream));
+                C->ev_launches.push_back(ns);   // one launch covers ns steps; report per step
+                C->timed_cells = h.ncell * h.ninst;
+            }
+            HIP_OK(fold_slabs(C, l, h.step, ns));
+            h.step += ns;
+            h.flags_step = h.step;
+            k -= ns;
+        }
     }
     // resident sets: launches of at most 32768 steps
     for (const auto& rs : C->res_sets) {
@@ -768,7 +972,7 @@ int run_steps(sllg_ctx* C, int64_t nsteps)
             const int64_t ns = std::min<int64_t>(k, 32768);
             hipEvent_t e0 = nullptr, e1 = nullptr;
             const bool time_this = C->timing > 0 && !std::any_of(C->lv.begin(), C->lv.end(), [](const LevelHost& x) {
-                return x.plan == kPlanStream;
+                return x.plan == kPlanStream || x.plan == kPlanSlab;
             });
             if (time_this) {
                 e0 = next_event(C);
@@ -778,6 +982,7 @@ int run_steps(sllg_ctx* C, int64_t nsteps)
             HIP_OK(dispatch_res(C, rs, h0.step, ns));
             if (time_this) {
                 HIP_OK(hipEventRecord(e1, C->stream));
+                C->ev_launches.push_back(1);
                 int64_t cells = 0;
                 for (int l : rs.levels) cells += C->lv[l].ncell * C->lv[l].ninst;
                 C->timed_cells = cells * ns;
@@ -796,6 +1001,8 @@ int reset_state(sllg_ctx* C)
     HIP_OK(hipMemsetAsync(C->d_status, 0, sizeof(int) * 4, C->stream));
     HIP_OK(hipMemsetAsync(C->d_inst_cnt, 0, sizeof(uint32_t) * C->lay.ninst_total, C->stream));
     HIP_OK(hipMemsetAsync(C->d_launch_cnt, 0, sizeof(uint32_t) * (C->lv.size() + 1), C->stream));
+    if (C->lay.max_slabs > 0) HIP_OK(hipMemsetAsync(C->d_flags, 0, sizeof(uint32_t) * C->lay.max_slabs, C->stream));
+    for (LevelHost& h : C->lv) h.flags_step = 0;
     HIP_OK(hipMemsetAsync(C->d_records, 0, sizeof(double) * C->lay.rec_doubles, C->stream));
     int maxc = 1;
     for (const LevelHost& h : C->lv) maxc = (int)std::max<int64_t>(maxc, h.ncell);
@@ -809,6 +1016,8 @@ int reset_state(sllg_ctx* C)
 // Timing-based choice of the stream tile shape (a few steps per candidate),
 // cached per (dims, instances, device) for the process.
 std::map<std::tuple<int, int, int, int>, std::pair<int, int>> g_tuned;
+std::map<std::tuple<int, int, int, int>, double> g_tuned_ms;                      // best stream ms/step
+std::map<std::tuple<int, int, int, int>, std::tuple<int, int, double>> g_tuned_slab;  // kernel, tz, ms/step
 
 int tune_stream(sllg_ctx* C, int level)
 {
@@ -893,6 +1102,81 @@ int tune_stream(sllg_ctx* C, int level)
     h.shape = best.first;
     h.tz = best.second;
     g_tuned[key] = best;
+    g_tuned_ms[key] = best_t / reps;
+    return SLLG_OK;
+}
+
+// Timing-based choice of the slab kernel and thickness for a slab-eligible
+// level; returns the best ms per step in *best_ms (1e30 if none runs).
+int tune_slab(sllg_ctx* C, int level, double* best_ms)
+{
+    LevelHost& h = C->lv[level];
+    const auto key = std::make_tuple(h.in.nx, h.in.ny, h.in.nz, h.ninst);
+    *best_ms = 1e30;
+    auto it = g_tuned_slab.find(key);
+    if (it != g_tuned_slab.end()) {
+        h.slab_kernel = std::get<0>(it->second);
+        h.slab_tz = std::get<1>(it->second);
+        *best_ms = std::get<2>(it->second);
+        return SLLG_OK;
+    }
+    const int P = h.in.nx * h.in.ny;
+    const int saved_plan = h.plan;
+    const int tzs[] = {2, 3, 4, 5, 6, 8, 10, 12, 14, 16, 20, 24, 28, 32};
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    int best_k = -1, best_tz = 0;
+    for (int ki = 0; ki < kNumSlabKernels; ++ki) {
+        const int NPP = kSlabKernels[ki].nt / P;
+        if (NPP < 1) continue;
+        const int cap = kSlabKernels[ki].k * NPP;
+        for (int tz : tzs) {
+            if (tz + 3 > cap || tz > h.in.nz) continue;
+            if ((kSlabKernels[ki].k - 1) * NPP >= tz + 3) continue;   // an idle cell slot per thread
+            h.plan = kPlanSlab;
+            h.slab_kernel = ki;
+            h.slab_tz = tz;
+            int rc = replan(C);
+            if (rc) return rc;
+            bool fits = false;
+            if (dispatch_slab(C, level, 0, 1, true, &fits) != hipSuccess || !fits) continue;
+            h.step = 0;
+            rc = sync_slab_flags(C, h);
+            if (rc) return rc;
+            HIP_OK(dispatch_slab(C, level, 0, 16));
+            HIP_OK(hipEventRecord(e0, C->stream));
+            HIP_OK(dispatch_slab(C, level, 16, 64));
+            HIP_OK(hipEventRecord(e1, C->stream));
+            HIP_OK(hipEventSynchronize(e1));
+            h.flags_step = -1;
+            float ms = 0;
+            HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+            if (getenv("SLLG_TUNE_VERBOSE"))
+                fprintf(stderr, "tune level %d: slab kernel %d (%d,%d) tz %d slabs %d: %.2f us/step\n", level, ki,
+                        kSlabKernels[ki].nt, kSlabKernels[ki].k, tz, h.nslab, 1000.0 * ms / 64);
+            if (ms / 64 < *best_ms) {
+                *best_ms = ms / 64;
+                best_k = ki;
+                best_tz = tz;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h.plan = saved_plan;
+    h.step = 0;
+    if (best_k >= 0) {
+        h.slab_kernel = best_k;
+        h.slab_tz = best_tz;
+        g_tuned_slab[key] = std::make_tuple(best_k, best_tz, *best_ms);
+    }
+    int rc = replan(C);
+    if (rc) return rc;
+    HIP_OK(hipStreamSynchronize(C->stream));
+    int st[4] = {0, 0, 0, 0};
+    HIP_OK(hipMemcpy(st, C->d_status, sizeof(st), hipMemcpyDeviceToHost));
+    if (st[0] & 2) return fail(SLLG_E_HIP, "slab exchange timed out while tuning");
     return SLLG_OK;
 }
 
@@ -1048,6 +1332,12 @@ int sllg_init(const sllg_material* mat, const sllg_level* levels, int32_t n_leve
     C->d_lam = (float*)(C->ws + L.lam);
     C->d_weights = (double*)(C->ws + L.weights);
     C->d_grads = (double*)(C->ws + L.grads);
+    C->d_slabs = (SlabDev*)(C->ws + L.slabs);
+    C->d_xch = (float*)(C->ws + L.xch);
+    C->d_flags = (uint32_t*)(C->ws + L.flags);
+    C->d_spart = (double*)(C->ws + L.spart);
+    C->d_islab = (int32_t*)(C->ws + L.islab);
+    C->h_islab.assign(2 * (size_t)L.ninst_total, 0);
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
@@ -1115,6 +1405,20 @@ int sllg_init(const sllg_material* mat, const sllg_level* levels, int32_t n_leve
             }
             tuned = true;
         }
+    for (int i = 0; i < n_levels; ++i) {
+        LevelHost& h = C->lv[i];
+        if (h.plan != kPlanStream || !slab_eligible(h.in) || getenv("SLLG_NO_SLAB")) continue;
+        double slab_ms = 1e30;
+        rc = tune_slab(C, i, &slab_ms);
+        if (rc) {
+            delete C;
+            return rc;
+        }
+        const auto key = std::make_tuple(h.in.nx, h.in.ny, h.in.nz, h.ninst);
+        const double stream_ms = g_tuned_ms.count(key) ? g_tuned_ms[key] : 1e30;
+        if (slab_ms < stream_ms) h.plan = kPlanSlab;
+        tuned = true;
+    }
     if (tuned) {
         rc = replan(C);
         if (!rc) rc = reset_state(C);
@@ -1228,7 +1532,9 @@ int sllg_level_params(const sllg_ctx* C, int32_t level, double out[16])
     const LevelHost& h = C->lv[level];
     const double v[16] = {h.zeta, h.A, h.K, h.Ms, h.a, h.c_ex, h.hk, h.gamma1, h.alpha, h.sigma, h.dt,
                           h.hscale, h.cM, (double)h.n_steps, h.hz_amp,
-                          (double)(h.plan * 100000 + (h.plan == kPlanStream ? h.shape * 1000 + h.tz : 0))};
+                          (double)(h.plan * 100000 + (h.plan == kPlanStream ? h.shape * 1000 + h.tz
+                                                      : h.plan == kPlanSlab ? h.slab_kernel * 1000 + h.slab_tz
+                                                                            : 0))};
     std::memcpy(out, v, sizeof(v));
     return SLLG_OK;
 }
@@ -1286,6 +1592,24 @@ int sllg_set_plan(sllg_ctx* C, int32_t level, int32_t plan)
         if (!resident_fits(h, C->max_lds)) return fail(SLLG_E_INVAL, "level %d does not fit in LDS", level);
         h.forced = 1;
     } else if (plan == kPlanStream) {
+        h.forced = 1;
+    } else if (plan == kPlanSlab) {
+        if (!slab_eligible(h.in)) return fail(SLLG_E_INVAL, "level %d cannot use slabs (nx*ny <= 1024, nz >= 4)", level);
+        auto it = g_tuned_slab.find(std::make_tuple(h.in.nx, h.in.ny, h.in.nz, h.ninst));
+        if (it != g_tuned_slab.end()) {
+            h.slab_kernel = std::get<0>(it->second);
+            h.slab_tz = std::get<1>(it->second);
+        } else {
+            // the smallest kernel that holds two-plane slabs
+            const int P = h.in.nx * h.in.ny;
+            h.slab_kernel = -1;
+            for (int ki = 0; ki < kNumSlabKernels && h.slab_kernel < 0; ++ki)
+                if (kSlabKernels[ki].nt / P >= 1 && kSlabKernels[ki].k * (kSlabKernels[ki].nt / P) >= 5) {
+                    h.slab_kernel = ki;
+                    h.slab_tz = 2;
+                }
+            if (h.slab_kernel < 0) return fail(SLLG_E_INVAL, "no slab kernel for level %d", level);
+        }
         h.forced = 1;
     } else {
         return fail(SLLG_E_INVAL, "unknown plan %d", plan);
@@ -1358,7 +1682,8 @@ int sllg_set_timing(sllg_ctx* C, int32_t on)
     if (!C) return fail(SLLG_E_INVAL, "null context");
     C->timing = on > 0 ? on : 0;
     C->ev_used = 0;
-    C->launch_counter = 0;
+    C->ev_launches.clear();
+    C->unit_counter = 0;
     return SLLG_OK;
 }
 
@@ -1367,16 +1692,19 @@ int sllg_kernel_time(sllg_ctx* C, double* mean_ms, int64_t* launches, int64_t* c
     if (!C) return fail(SLLG_E_INVAL, "null context");
     HIP_OK(hipStreamSynchronize(C->stream));
     double tot = 0;
-    const int64_t nl = (int64_t)(C->ev_used / 2);
-    for (int64_t i = 0; i < nl; ++i) {
+    int64_t nl = 0;
+    const int64_t np = (int64_t)(C->ev_used / 2);
+    for (int64_t i = 0; i < np && i < (int64_t)C->ev_launches.size(); ++i) {
         float ms = 0;
         HIP_OK(hipEventElapsedTime(&ms, C->ev_pool[2 * i], C->ev_pool[2 * i + 1]));
         tot += ms;
+        nl += C->ev_launches[i];
     }
     if (mean_ms) *mean_ms = nl ? tot / nl : 0.0;
     if (launches) *launches = nl;
     if (cells_per_launch) *cells_per_launch = C->timed_cells;
     C->ev_used = 0;
+    C->ev_launches.clear();
     return SLLG_OK;
 }
 

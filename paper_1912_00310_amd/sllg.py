@@ -19,7 +19,7 @@ SLLG_OK = 0
 ERRORS = {-1: "SLLG_E_INVAL", -2: "SLLG_E_WORKSPACE", -3: "SLLG_E_CAPACITY",
           -4: "SLLG_E_STATE", -5: "SLLG_E_HIP", -6: "SLLG_E_NUMERIC"}
 WAVES = {"triangle": 0, "cosine": 1, "constant": 2}
-PLAN_AUTO, PLAN_RESIDENT, PLAN_STREAM = 0, 1, 2
+PLAN_AUTO, PLAN_RESIDENT, PLAN_STREAM, PLAN_SLAB = 0, 1, 2, 3
 
 
 class SllgError(RuntimeError):

@@ -167,3 +167,61 @@ def test_realizations_are_independent_streams(P, orc):
         m_ref, _ = orc.run(lv, 11 + r, 0, 100, np.tile([0.0, 0.0, 1.0], (N, 1)))
         assert np.abs(gpu_state(sim, 0, r) - m_ref).max() < 1e-5
     sim.close()
+
+
+# ---- persistent z-slab plan (workgroups of one realization exchange planes)
+
+
+
+def test_slab_plan_matches_oracle_and_other_plans(P, orc):
+    wl = W.workload("rod_b1_ens8")
+    wl["levels"][0]["n_real"] = 2
+    out = {}
+    for plan in (P.PLAN_STREAM, P.PLAN_SLAB):
+        sim = P.Sim(wl["material"], wl["levels"])
+        sim.set_plan(0, plan)
+        sim.run_steps(300)
+        out[plan] = (sim.get_state(0, 1), sim.loop(0, 1)[1])
+        sim.close()
+    assert np.array_equal(out[P.PLAN_STREAM][0], out[P.PLAN_SLAB][0])
+    assert np.abs(out[P.PLAN_STREAM][1] - out[P.PLAN_SLAB][1]).max() < 1e-6
+    lv = oracle_level(wl)
+    N = lv["nx"] * lv["ny"] * lv["nz"]
+    m_ref, mb = orc.run(lv, 2, 0, 300, np.tile([0.0, 0.0, 1.0], (N, 1)))
+    assert np.abs(out[P.PLAN_SLAB][0].T - m_ref).max() < 1e-5
+    assert np.abs(out[P.PLAN_SLAB][1] - mb).max() < 2e-6
+
+
+@pytest.mark.parametrize("dims", [(5, 7, 11), (8, 24, 5), (3, 2, 4)])
+def test_slab_plan_ragged(P, orc, dims):
+    wl = W.workload("block_b2_cone10")
+    wl["levels"][0].update(nx=dims[0], ny=dims[1], nz=dims[2], n_real=2)
+    wl["material"]["sweep_Oe_per_ns"] = 1e5
+    lv = oracle_level(wl)
+    sim = P.Sim(wl["material"], wl["levels"])
+    sim.set_plan(0, P.PLAN_SLAB)
+    u = orc.make_axes(lv)
+    N = lv["nx"] * lv["ny"] * lv["nz"]
+    m_ref = [np.tile([0.0, 0.0, 1.0], (N, 1)) for _ in range(2)]
+    for n in range(0, 150, 50):
+        sim.run_steps(50)
+        for r in range(2):
+            m_ref[r], _ = orc.run(lv, 1 + r, n, 50, m_ref[r], u=u)
+            assert np.abs(gpu_state(sim, 0, r) - m_ref[r]).max() < 1e-5, (dims, n, r)
+    sim.close()
+
+
+def test_slab_plan_chunks_and_checkpoints(P):
+    # more steps than one slab launch holds, checkpoints written by the slab kernel
+    wl = W.workload("rod_b4_adjoint64")
+    wl["material"]["sweep_Oe_per_ns"] *= 20          # 2000 steps
+    wl["levels"][0]["n_real"] = 2
+    res = {}
+    for plan in (P.PLAN_RESIDENT, P.PLAN_SLAB):
+        sim = P.Sim(wl["material"], wl["levels"], ckpt_every=256)
+        sim.set_plan(0, plan)
+        sim.run_sweep()
+        res[plan] = (sim.get_state(0, 1), sim.grad(0))
+        sim.close()
+    assert np.array_equal(res[P.PLAN_RESIDENT][0], res[P.PLAN_SLAB][0])
+    assert np.allclose(res[P.PLAN_RESIDENT][1][0], res[P.PLAN_SLAB][1][0], rtol=1e-5)
