@@ -166,11 +166,10 @@ __device__ __forceinline__ V3 thermal_field(const LevelDev& L, uint64_t seed, ui
 // ---------------------------------------------------------------------------
 // Online loop accumulation for one instance at step n -> n+1 (FP64).
 // ---------------------------------------------------------------------------
-__device__ inline void loop_accumulate(AccDev& a, const LevelDev& L, int64_t n, double m_new,
-                                       double* rec)
+// h0, h1: simulated field (Oe) at steps n and n + 1.
+__device__ inline void loop_accumulate_h(AccDev& a, const LevelDev& L, double h0, double h1, double m_new,
+                                         double* rec)
 {
-    const double h0 = L.hz_oe * wave_at(L, n);
-    const double h1 = L.hz_oe * wave_at(L, n + 1);
     const double dH = h1 - h0;
     const double m0 = a.m_prev;
     a.area -= 0.5 * (m0 + m_new) * dH;
@@ -201,6 +200,11 @@ __device__ inline void loop_accumulate(AccDev& a, const LevelDev& L, int64_t n, 
         a.rec_phase = 0;
         if (a.rec_idx + 1 < L.n_rec) rec[++a.rec_idx] = m_new;   // never past the record
     }
+}
+
+__device__ inline void loop_accumulate(AccDev& a, const LevelDev& L, int64_t n, double m_new, double* rec)
+{
+    loop_accumulate_h(a, L, L.hz_oe * wave_at(L, n), L.hz_oe * wave_at(L, n + 1), m_new, rec);
 }
 
 // Wave-wide FP32 sum (all 64 lanes end with the total).

@@ -60,7 +60,7 @@ constexpr double kGamma0 = kMu0 * kGammaE;
 constexpr double kOe = 1000.0 / (4.0 * kPi);   // A/m per Oe
 
 constexpr int kPlanAuto = 0, kPlanResident = 1, kPlanStream = 2, kPlanSlab = 3;
-constexpr int kSlabChunk = 1024;   // steps per slab-plan launch (partials buffer depth)
+static_assert(kSlabChunk < 2048, "slab exchange tags hold the step of a launch in 11 bits");
 
 // Compiled FP64 constants of one level.
 struct LevelHost {
@@ -80,8 +80,7 @@ struct LevelHost {
     int slab_kernel;      // index into kSlabKernels
     int slab_tz;
     int slab0, nslab;     // slab table range
-    int64_t xch_off;      // float offset of the level's exchange buffer
-    int64_t flags_step;   // step the slab flags currently hold (-1: unknown)
+    int64_t xch_off;      // word offset of the level's exchange buffer
     int64_t step;         // host view of the step index
 };
 
@@ -114,10 +113,10 @@ const ResidentKernel kResKernels[] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {16, 1}, {
 // Layout of the workspace (byte offsets).
 struct Layout {
     size_t levels, insts, accs, steps, status, inst_cnt, launch_cnt, partials, tiles, groups, slots,
-        chunks, buf0, buf1, axes, records, ckpt, tape, lam, weights, grads, slabs, xch, flags, spart,
-        islab, total;
+        chunks, buf0, buf1, axes, records, ckpt, tape, lam, weights, grads, slabs, xch, spart, islab,
+        total;
     int64_t state_floats, axes_floats, rec_doubles, ckpt_floats, tape_floats, lam_floats,
-        max_tiles, max_groups, max_chunks, max_w, ninst_total, max_slabs, xch_floats;
+        max_tiles, max_groups, max_chunks, max_w, ninst_total, max_slabs, xch_words;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -199,8 +198,8 @@ struct sllg_ctx {
     double* d_weights = nullptr;
     double* d_grads = nullptr;
     SlabDev* d_slabs = nullptr;
-    float* d_xch = nullptr;
-    uint32_t* d_flags = nullptr;
+    uint64_t* d_xch = nullptr;
+    uint32_t slab_seq = 0;        // slab launches so far (exchange tags)
     double* d_spart = nullptr;
     int32_t* d_islab = nullptr;   // per instance: first slab (level-relative), then slab count
     std::vector<SlabDev> h_slabs;
@@ -369,7 +368,7 @@ Layout make_layout(const sllg_material& m, const std::vector<LevelHost>& lv, int
         if (slab_eligible(h.in)) {
             const int64_t ns = (int64_t)(h.in.nz / 2) * h.in.n_real;
             L.max_slabs += ns;
-            L.xch_floats += 2 * ns * 12 * (int64_t)h.in.nx * h.in.ny;
+            L.xch_words += 2 * ns * 12 * (int64_t)h.in.nx * h.in.ny;
         }
     }
     (void)m;
@@ -412,8 +411,7 @@ Layout make_layout(const sllg_material& m, const std::vector<LevelHost>& lv, int
     L.weights = take(sizeof(double) * 2 * maxw);
     L.grads = take(sizeof(double) * 10 * ninst);
     L.slabs = take(sizeof(SlabDev) * L.max_slabs);
-    L.xch = take(sizeof(float) * L.xch_floats);
-    L.flags = take(sizeof(uint32_t) * L.max_slabs);
+    L.xch = take(sizeof(uint64_t) * L.xch_words);
     L.spart = take(sizeof(double) * L.max_slabs * kSlabChunk);
     L.islab = take(sizeof(int32_t) * 2 * ninst);
     L.total = o;
@@ -611,7 +609,12 @@ int upload_tables(sllg_ctx* C)
 }
 
 // Slabs of every instance of a slab-plan level: nz split into runs of
-// slab_tz or slab_tz + 1 planes (each at least 2).
+// slab_tz or slab_tz + 1 planes (each at least 2).  Workgroups are handed to
+// the 8 XCDs round-robin by block index, so the slabs of one instance are
+// placed at block indices of one residue mod 8 where the counts allow: their
+// exchanges then stay within one XCD.  The order only affects speed.
+constexpr int kXcds = 8;
+
 void build_slabs(sllg_ctx* C, LevelHost& h)
 {
     h.slab0 = (int)C->h_slabs.size();
@@ -621,25 +624,42 @@ void build_slabs(sllg_ctx* C, LevelHost& h)
     // slab then has at most tz + 1 planes
     const int nsl = std::max(1, std::min((nz + tz - 1) / tz, nz / 2));
     const int base = nz / nsl, extra = nz % nsl;
+    const int total = nsl * h.ninst;
+    // lid = r * nsl + k  ->  block index
+    std::vector<std::vector<int>> bins(kXcds);
+    for (int r = 0; r < h.ninst; ++r)
+        for (int k = nsl - 1; k >= 0; --k) bins[r % kXcds].push_back(r * nsl + k);   // popped from the back
+    std::vector<int> block_of(total);
+    for (int b = 0; b < total; ++b) {
+        int pick = b % kXcds;
+        if (bins[pick].empty())
+            pick = (int)(std::max_element(bins.begin(), bins.end(),
+                                          [](const std::vector<int>& a, const std::vector<int>& c) {
+                                              return a.size() < c.size();
+                                          }) - bins.begin());
+        block_of[bins[pick].back()] = b;
+        bins[pick].pop_back();
+    }
+    std::vector<SlabDev> tab(total);
     for (int r = 0; r < h.ninst; ++r) {
-        const int first = (int)C->h_slabs.size() - h.slab0;
-        C->h_islab[2 * (h.inst0 + r)] = first;
+        C->h_islab[2 * (h.inst0 + r)] = r * nsl;
         C->h_islab[2 * (h.inst0 + r) + 1] = nsl;
         int z0 = 0;
         for (int k = 0; k < nsl; ++k) {
+            const int lid = r * nsl + k;
             SlabDev d{};
             d.inst = h.inst0 + r;
             d.z0 = z0;
             d.nzs = base + (k < extra ? 1 : 0);
-            d.prev = k > 0 ? first + k - 1 : -1;
-            d.next = k + 1 < nsl ? first + k + 1 : -1;
-            d.slab0 = first;
+            d.prev = k > 0 ? block_of[lid - 1] : -1;
+            d.next = k + 1 < nsl ? block_of[lid + 1] : -1;
+            d.lid = lid;
             z0 += d.nzs;
-            C->h_slabs.push_back(d);
+            tab[block_of[lid]] = d;
         }
     }
-    h.nslab = (int)C->h_slabs.size() - h.slab0;
-    h.flags_step = -1;
+    C->h_slabs.insert(C->h_slabs.end(), tab.begin(), tab.end());
+    h.nslab = total;
 }
 
 int replan(sllg_ctx* C)
@@ -655,7 +675,7 @@ int replan(sllg_ctx* C)
             xo += 2LL * h.nslab * 12 * h.in.nx * h.in.ny;
         }
     }
-    if ((int64_t)C->h_slabs.size() > C->lay.max_slabs || xo > C->lay.xch_floats)
+    if ((int64_t)C->h_slabs.size() > C->lay.max_slabs || xo > C->lay.xch_words)
         return fail(SLLG_E_WORKSPACE, "slab tables exceed the reserved workspace");
     if (!C->h_slabs.empty()) {
         HIP_OK(hipMemcpyAsync(C->d_slabs, C->h_slabs.data(), sizeof(SlabDev) * C->h_slabs.size(),
@@ -794,14 +814,21 @@ hipError_t launch_slab_t(sllg_ctx* C, int level, int64_t n0, int ns, bool check_
     float* b0 = C->d_buf0;
     float* b1 = C->d_buf1;
     const float* axes = C->d_axes;
-    float* xch = C->d_xch + h.xch_off;
-    uint32_t* flags = C->d_flags + h.slab0;
+    uint64_t* xch = C->d_xch + h.xch_off;
+    // tags of this launch: (sequence mod 2^21) << 11 | step + 1; the buffer is
+    // cleared whenever the sequence wraps, so a stale word never matches
+    const uint32_t seq = C->slab_seq++ & 0x1FFFFFu;
+    if (seq == 0) {
+        e = hipMemsetAsync(C->d_xch, 0, sizeof(uint64_t) * (size_t)C->lay.xch_words, C->stream);
+        if (e != hipSuccess) return e;
+    }
+    uint32_t tag_base = seq << 11;
     double* part = C->d_spart + (int64_t)h.slab0 * kSlabChunk;
     int pstride = kSlabChunk;
     float* ckpt = C->d_ckpt;
     int ck = C->ckpt_every;
     int* status = C->d_status;
-    void* args[] = {&slabs, &insts, &levels, &b0, &b1, &axes, &xch, &flags, &part, &pstride, &ckpt, &ck,
+    void* args[] = {&slabs, &insts, &levels, &b0, &b1, &axes, &xch, &tag_base, &part, &pstride, &ckpt, &ck,
                     &n0, &ns, &status};
     return hipLaunchCooperativeKernel(fn, dim3((unsigned)h.nslab), dim3(NT), args, (unsigned)lds, C->stream);
 }
@@ -823,22 +850,10 @@ hipError_t dispatch_slab(sllg_ctx* C, int level, int64_t n0, int ns, bool check_
     }
 }
 
-// the flags of a level's slabs must hold the current step before a launch
-int sync_slab_flags(sllg_ctx* C, LevelHost& h)
-{
-    if (h.flags_step == h.step) return SLLG_OK;
-    std::vector<uint32_t> f((size_t)h.nslab, (uint32_t)h.step);
-    HIP_OK(hipMemcpyAsync(C->d_flags + h.slab0, f.data(), sizeof(uint32_t) * f.size(), hipMemcpyHostToDevice,
-                          C->stream));
-    HIP_OK(hipStreamSynchronize(C->stream));
-    h.flags_step = h.step;
-    return SLLG_OK;
-}
-
 hipError_t fold_slabs(sllg_ctx* C, int level, int64_t n0, int ns)
 {
     const LevelHost& h = C->lv[level];
-    hipLaunchKernelGGL(k_fold_slabs, dim3((unsigned)h.ninst), dim3(64), 0, C->stream, C->d_insts, h.inst0,
+    hipLaunchKernelGGL(k_fold_slabs<256>, dim3((unsigned)h.ninst), dim3(256), 0, C->stream, C->d_insts, h.inst0,
                        C->d_islab + 2 * h.inst0, C->d_levels, C->d_spart + (int64_t)h.slab0 * kSlabChunk,
                        kSlabChunk, n0, ns, C->d_accs, C->d_records, C->d_status);
     return hipGetLastError();
@@ -939,8 +954,6 @@ int run_steps(sllg_ctx* C, int64_t nsteps)
     for (int l = 0; l < (int)C->lv.size(); ++l) {
         LevelHost& h = C->lv[l];
         if (h.plan != kPlanSlab) continue;
-        int rc = sync_slab_flags(C, h);
-        if (rc) return rc;
         int64_t k = std::min(nsteps, h.n_steps - h.step);
         while (k > 0) {
             const int ns = (int)std::min<int64_t>(k, kSlabChunk);
@@ -960,7 +973,6 @@ int run_steps(sllg_ctx* C, int64_t nsteps)
             }
             HIP_OK(fold_slabs(C, l, h.step, ns));
             h.step += ns;
-            h.flags_step = h.step;
             k -= ns;
         }
     }
@@ -1001,8 +1013,6 @@ int reset_state(sllg_ctx* C)
     HIP_OK(hipMemsetAsync(C->d_status, 0, sizeof(int) * 4, C->stream));
     HIP_OK(hipMemsetAsync(C->d_inst_cnt, 0, sizeof(uint32_t) * C->lay.ninst_total, C->stream));
     HIP_OK(hipMemsetAsync(C->d_launch_cnt, 0, sizeof(uint32_t) * (C->lv.size() + 1), C->stream));
-    if (C->lay.max_slabs > 0) HIP_OK(hipMemsetAsync(C->d_flags, 0, sizeof(uint32_t) * C->lay.max_slabs, C->stream));
-    for (LevelHost& h : C->lv) h.flags_step = 0;
     HIP_OK(hipMemsetAsync(C->d_records, 0, sizeof(double) * C->lay.rec_doubles, C->stream));
     int maxc = 1;
     for (const LevelHost& h : C->lv) maxc = (int)std::max<int64_t>(maxc, h.ncell);
@@ -1142,14 +1152,11 @@ int tune_slab(sllg_ctx* C, int level, double* best_ms)
             bool fits = false;
             if (dispatch_slab(C, level, 0, 1, true, &fits) != hipSuccess || !fits) continue;
             h.step = 0;
-            rc = sync_slab_flags(C, h);
-            if (rc) return rc;
             HIP_OK(dispatch_slab(C, level, 0, 16));
             HIP_OK(hipEventRecord(e0, C->stream));
             HIP_OK(dispatch_slab(C, level, 16, 64));
             HIP_OK(hipEventRecord(e1, C->stream));
             HIP_OK(hipEventSynchronize(e1));
-            h.flags_step = -1;
             float ms = 0;
             HIP_OK(hipEventElapsedTime(&ms, e0, e1));
             if (getenv("SLLG_TUNE_VERBOSE"))
@@ -1333,8 +1340,7 @@ int sllg_init(const sllg_material* mat, const sllg_level* levels, int32_t n_leve
     C->d_weights = (double*)(C->ws + L.weights);
     C->d_grads = (double*)(C->ws + L.grads);
     C->d_slabs = (SlabDev*)(C->ws + L.slabs);
-    C->d_xch = (float*)(C->ws + L.xch);
-    C->d_flags = (uint32_t*)(C->ws + L.flags);
+    C->d_xch = (uint64_t*)(C->ws + L.xch);
     C->d_spart = (double*)(C->ws + L.spart);
     C->d_islab = (int32_t*)(C->ws + L.islab);
     C->h_islab.assign(2 * (size_t)L.ninst_total, 0);

@@ -8,16 +8,18 @@
 //      each side) from m_n in LDS, which holds planes z0-2 .. z0+nzs+1;
 //   2. corrects its own planes from m' in LDS and writes m_{n+1} over m_n;
 //   3. publishes its first two and last two planes of m_{n+1} into a
-//      step-parity exchange buffer with agent-coherent stores, waits for the
-//      stores, then publishes its step count in a flag;
-//   4. waits for the flags of its z neighbours and copies their boundary
-//      planes into its LDS halo.
-// Neighbouring workgroups therefore never drift apart by more than one step,
-// and the double-buffered exchange has no write-after-read hazard.  The
-// per-step partial sums of m_z go to a [workgroup][step] buffer that a fold
-// kernel turns into loops after the launch.  The launch is cooperative (all
-// workgroups resident); every wait is bounded and a timeout sets a status
-// bit and ends the kernel.
+//      step-parity exchange buffer as 64-bit words (value, tag), each written
+//      by one agent-coherent store, the tag naming the launch and the step;
+//   4. polls the words its z neighbours publish for the same step until every
+//      tag matches, and puts their values into its LDS halo.
+// A word carries its own step tag, so no separate flag or store
+// acknowledgement is needed: one trip through device memory per step.
+// Neighbouring workgroups never drift apart by more than one step, so the
+// double-buffered exchange has no write-after-read hazard.  The per-step
+// partial sums of m_z go to a [slab][step] buffer that a fold kernel turns
+// into loops after the launch.  The launch is cooperative (all workgroups
+// resident); every wait is bounded and a timeout sets a status bit and ends
+// the kernel.
 #include <hip/hip_runtime.h>
 
 #include "sllg_device.hpp"
@@ -28,25 +30,33 @@ namespace sllg {
 struct SlabDev {
     int32_t inst;
     int32_t z0, nzs;
-    int32_t prev, next;   // slab below / above (-1 at the grid ends)
-    int32_t slab0;        // first slab of the instance
+    int32_t prev, next;   // workgroup of the slab below / above (-1 at the grid ends)
+    int32_t lid;          // slab index in instance order (row of the partials buffer)
     int32_t pad0, pad1;
 };
 
-__device__ __forceinline__ void st_agent(float* p, float v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ float ld_agent(const float* p)
-{
-    return __hip_atomic_load(const_cast<float*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+constexpr uint32_t kSlabSpinLimit = 1u << 20;
+constexpr int kSlabChunk = 1024;   // steps per launch (depth of the partials buffer)
 
+__device__ __forceinline__ void st_word(uint64_t* p, float v, uint32_t tag)
+{
+    const uint64_t w = static_cast<uint64_t>(__float_as_uint(v)) | (static_cast<uint64_t>(tag) << 32);
+    __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_word(const uint64_t* p)
+{
+    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t word_tag(uint64_t w) { return static_cast<uint32_t>(w >> 32); }
+__device__ __forceinline__ float word_val(uint64_t w) { return __uint_as_float(static_cast<uint32_t>(w)); }
+
+// tag of the words published at step st of a launch: tag_base + st + 1,
+// tag_base = (launch sequence number mod 2^21) << 11, st < 2048
 template <int NT, int K>
 __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, const InstDev* __restrict__ insts,
                                              const LevelDev* __restrict__ levels, float* __restrict__ buf0,
                                              float* __restrict__ buf1, const float* __restrict__ axes,
-                                             float* __restrict__ xch, uint32_t* __restrict__ flags,
+                                             uint64_t* __restrict__ xch, uint32_t tag_base,
                                              double* __restrict__ partials, int pstride, float* __restrict__ ckpt,
                                              int ckpt_every, int64_t n0, int nsteps, int* __restrict__ status)
 {
@@ -72,10 +82,9 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
     auto mn = [&](int me, int k) -> float& { return Mn[(me * 3 + k) * P + c]; };
     const int ixm = x > 0 ? c - 1 : c, ixp = x < nx - 1 ? c + 1 : c;
     const int iym = y > 0 ? c - nx : c, iyp = y < ny - 1 ? c + nx : c;
-    // exchange slot of one plane of one slab at a step parity
-    const int64_t XS = 4LL * 3 * P;
+    // exchange slot (3 x P words) of one plane of one slab at a step parity
     auto xslot = [&](int par, int slab, int slot) {
-        return xch + (static_cast<int64_t>(par) * gridDim.x + slab) * XS + static_cast<int64_t>(slot) * 3 * P;
+        return xch + ((static_cast<int64_t>(par) * gridDim.x + slab) * 4 + slot) * 3 * P;
     };
     if (tid == 0) s_abort = 0;
 
@@ -132,9 +141,11 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
             }
         }
         __syncthreads();
-        // ---- 2. corrector on own planes; m_{n+1} replaces m_n in LDS
+        // ---- 2. corrector on own planes; m_{n+1} replaces m_n in LDS and
+        //         the boundary planes go out as tagged words
         float msum = 0.0f;
         const int par = static_cast<int>((n + 1) & 1);
+        const uint32_t tag = tag_base + static_cast<uint32_t>(st) + 1u;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int e = r + j * NPP;
@@ -156,58 +167,61 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
             mn(me, 1) = mnew.y;
             mn(me, 2) = mnew.z;
             msum += mnew.z;
-            // boundary planes for the neighbours: slots 0, 1 = first two, 2, 3 = last two
+            // slots 0, 1 = first two planes, 2, 3 = last two
             if (e <= 2) {
-                float* d = xslot(par, sid, e - 1);
-                st_agent(d + c, mnew.x);
-                st_agent(d + P + c, mnew.y);
-                st_agent(d + 2 * P + c, mnew.z);
+                uint64_t* d = xslot(par, sid, e - 1);
+                st_word(d + c, mnew.x, tag);
+                st_word(d + P + c, mnew.y, tag);
+                st_word(d + 2 * P + c, mnew.z, tag);
             }
             if (e >= nzs - 1) {
-                float* d = xslot(par, sid, 2 + (e - (nzs - 1)));
-                st_agent(d + c, mnew.x);
-                st_agent(d + P + c, mnew.y);
-                st_agent(d + 2 * P + c, mnew.z);
+                uint64_t* d = xslot(par, sid, 2 + (e - (nzs - 1)));
+                st_word(d + c, mnew.x, tag);
+                st_word(d + P + c, mnew.y, tag);
+                st_word(d + 2 * P + c, mnew.z, tag);
             }
         }
-        const double tot = block_sum<NT>(msum, red);   // contains a barrier
-        if (tid == 0) partials[static_cast<int64_t>(sid) * pstride + st] = tot;
-        // ---- 3. publish: every thread's exchange stores complete, then the flag
-        __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
-        if (tid == 0) {
-            const uint32_t want = static_cast<uint32_t>(n + 1);
-            __hip_atomic_store(&flags[sid], want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            // ---- 4. wait for the z neighbours (bounded)
-            for (int k = 0; k < 2; ++k) {
-                const int nb = k == 0 ? S.prev : S.next;
-                if (nb < 0) continue;
-                uint32_t spins = 0;
-                while (static_cast<int32_t>(__hip_atomic_load(&flags[nb], __ATOMIC_RELAXED,
-                                                              __HIP_MEMORY_SCOPE_AGENT) - want) < 0) {
-                    __builtin_amdgcn_s_sleep(2);
-                    if (++spins > (1u << 20)) {
-                        s_abort = 1;
-                        atomicOr(status, 2);
-                        break;
-                    }
-                }
-            }
+        {
+            const float ws = wave_sum(msum);
+            if ((tid & 63) == 0) red[tid >> 6] = static_cast<double>(ws);
         }
-        __syncthreads();
-        if (s_abort) return;
-        // halo planes z0-2, z0-1 from the slab below; z0+nzs, z0+nzs+1 from above
-        for (int h = r; h < 4; h += NPP) {
-            if (!lane_on) break;
+        // ---- 3. halo planes z0-2, z0-1 from the slab below, z0+nzs, z0+nzs+1
+        //         from above, once every word carries this step's tag (bounded)
+        for (int h = r; h < 4 && lane_on; h += NPP) {
             const int me = h < 2 ? h : nzs + h;   // 0, 1, nzs+2, nzs+3
             const int z = z0 - 2 + me;
             if (z < 0 || z >= nz) continue;
-            const float* s = h < 2 ? xslot(par, S.prev, 2 + h) : xslot(par, S.next, h - 2);
-            mn(me, 0) = ld_agent(s + c);
-            mn(me, 1) = ld_agent(s + P + c);
-            mn(me, 2) = ld_agent(s + 2 * P + c);
+            const uint64_t* s = h < 2 ? xslot(par, S.prev, 2 + h) : xslot(par, S.next, h - 2);
+            uint64_t w0, w1, w2;
+            uint32_t spins = 0;
+            bool ok = true;
+            for (;;) {
+                w0 = ld_word(s + c);
+                w1 = ld_word(s + P + c);
+                w2 = ld_word(s + 2 * P + c);
+                if (word_tag(w0) == tag && word_tag(w1) == tag && word_tag(w2) == tag) break;
+                if (++spins > kSlabSpinLimit) {
+                    ok = false;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (!ok) {
+                s_abort = 1;
+                atomicOr(status, 2);
+                break;
+            }
+            mn(me, 0) = word_val(w0);
+            mn(me, 1) = word_val(w1);
+            mn(me, 2) = word_val(w2);
         }
         __syncthreads();
+        if (s_abort) return;
+        if (tid == 0) {
+            double tot = 0.0;
+            for (int w = 0; w < NT / 64; ++w) tot += red[w];
+            partials[static_cast<int64_t>(S.lid) * pstride + st] = tot;
+        }
     }
     // ---- write back own planes at step n0 + nsteps
     float* mo = (((n0 + nsteps) & 1) ? buf1 : buf0) + I.state_off;
@@ -220,31 +234,40 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
     }
 }
 
-// Fold the per-step slab partials of one launch into the loops, one wave per
-// instance: lanes sum the slabs of a step in a fixed order, lane 0 folds.
-__global__ void k_fold_slabs(const InstDev* __restrict__ insts, int inst0, const int32_t* __restrict__ islab,
-                             const LevelDev* __restrict__ levels,
-                             const double* __restrict__ partials, int pstride, int64_t n0, int nsteps,
-                             AccDev* __restrict__ accs, double* __restrict__ records, int* __restrict__ status)
+// Fold the per-step slab partials of one launch into the loops, one block
+// per instance: first every thread sums the slabs of its steps in slab order
+// and evaluates the field, into LDS; then one lane runs the sequential FP64
+// loop accumulation over the launch's steps.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_fold_slabs(const InstDev* __restrict__ insts, int inst0,
+                                                   const int32_t* __restrict__ islab,
+                                                   const LevelDev* __restrict__ levels,
+                                                   const double* __restrict__ partials, int pstride, int64_t n0,
+                                                   int nsteps, AccDev* __restrict__ accs,
+                                                   double* __restrict__ records, int* __restrict__ status)
 {
+    __shared__ double mz[kSlabChunk];
+    __shared__ double hh[kSlabChunk + 1];
     const int k = static_cast<int>(blockIdx.x);
     const int inst = inst0 + k;
     const InstDev I = insts[inst];
     const LevelDev& L = levels[I.level];
     const int s0 = islab[2 * k], ns = islab[2 * k + 1];   // level-relative first slab, count
-    AccDev a;
-    if (threadIdx.x == 0) a = accs[inst];
-    for (int st = 0; st < nsteps; ++st) {
+    const double ncell = static_cast<double>(L.ncell);
+    for (int st = static_cast<int>(threadIdx.x); st <= nsteps; st += NT) {
+        hh[st] = L.hz_oe * wave_at(L, n0 + st);
+        if (st == nsteps) continue;
         double v = 0.0;
-        for (int s = static_cast<int>(threadIdx.x); s < ns; s += 64)
-            v += partials[static_cast<int64_t>(s0 + s) * pstride + st];
-        v = wave_sum_d(v);
-        if (threadIdx.x == 0) loop_accumulate(a, L, n0 + st, v / static_cast<double>(L.ncell), records + I.rec_off);
+        for (int s = 0; s < ns; ++s) v += partials[static_cast<int64_t>(s0 + s) * pstride + st];
+        mz[st] = v / ncell;
     }
-    if (threadIdx.x == 0) {
-        accs[inst] = a;
-        if (!isfinite(a.m_prev)) atomicOr(status, 1);
-    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    AccDev a = accs[inst];
+    double* rec = records + I.rec_off;
+    for (int st = 0; st < nsteps; ++st) loop_accumulate_h(a, L, hh[st], hh[st + 1], mz[st], rec);
+    accs[inst] = a;
+    if (!isfinite(a.m_prev)) atomicOr(status, 1);
 }
 
 }  // namespace sllg
