@@ -16,9 +16,11 @@ block_b2_cone10, rod_b4_adjoint64.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -112,7 +114,8 @@ def main():
         one_step()
     torch.cuda.synchronize()
     # HIP events on the library's stream around the dominant kernel's launch
-    # units (graph replays of 128 streamed steps, or resident launches)
+    # units (graph replays of 128 streamed steps, slab launches, or resident
+    # launches)
     sim.set_timing(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -129,25 +132,42 @@ def main():
     stats = {l: sim.loop(l, -1)[2] for l in range(len(levels))}
     plan_ids = [int(p["plan"]) for p in params]
 
-    # roofline of the dominant kernel from its mean launch time
+    # roofline of the dominant kernel from its mean launch time.  The library
+    # times streamed launches if a level is streamed, else slab launches, else
+    # resident launches; a slab launch covers kSlabChunk steps and the library
+    # reports it per step, so it is scaled back to one dispatch here.
     rl = None
+    kernels = [sim.kernel_name(l) for l in range(len(levels))]
+    fam = next((f for f in ("k_stream", "k_rows", "k_slab", "k_resident")
+                if any(k.startswith(f) for k in kernels)), "none")
+    if fam == "k_rows" and any(k.startswith("k_stream") for k in kernels):
+        fam = "k_stream"
+    dom = next(k for k in kernels if k.startswith(fam)) if fam != "none" else "none"
     if k_n > 0 and k_ms > 0:
-        per_launch = k_cells
+        spl = 1
+        mt = re.search(r"steps/launch (\d+)", dom)
+        if mt:
+            spl = int(mt.group(1))
+        launch_ms = k_ms * spl
+        per_launch = k_cells * spl
         has_axes = any(l.get("cone_deg", 0) > 0 for l in levels)
         bpc = BYTES_PER_CELL_UPDATE + (BYTES_AXES if has_axes else 0)
-        gbs = per_launch * bpc / (k_ms * 1e-3) / 1e9
-        tops = per_launch * VALU_OPS_PER_CELL_UPDATE / (k_ms * 1e-3) / 1e12
+        gbs = per_launch * bpc / (launch_ms * 1e-3) / 1e9
+        tops = per_launch * VALU_OPS_PER_CELL_UPDATE / (launch_ms * 1e-3) / 1e12
         f_h, f_a = gbs / PEAK_HBM_GBS, tops / PEAK_VALU_TOPS
+        traffic = measured_traffic(fam, a.workload)
         if f_h >= f_a:
             rl = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                  "frac": round(f_h, 4), "traffic": None}
+                  "frac": round(f_h, 4), "traffic": traffic}
         else:
             rl = {"bound": "alu", "achieved": round(tops, 3), "peak": round(PEAK_VALU_TOPS, 3),
-                  "unit": "TOP/s", "frac": round(f_a, 4), "traffic": None}
-        rl["kernel"] = "k_rows/k_stream" if any(p // 100000 == 2 for p in plan_ids) else "k_resident"
-        rl["mean_launch_ms"] = k_ms
-        rl["launches_timed"] = k_n
+                  "unit": "TOP/s", "frac": round(f_a, 4), "traffic": traffic}
+        rl["kernel"] = dom
+        rl["mean_launch_ms"] = launch_ms
+        rl["steps_per_launch"] = spl
+        rl["launches_timed"] = k_n // spl if spl > 1 else k_n
         rl["cell_updates_per_launch"] = per_launch
+        rl["algorithmic_bytes_per_launch"] = per_launch * bpc
         rl["hbm_equiv_GBps"] = round(gbs, 1)
         rl["valu_TOPs"] = round(tops, 3)
 
@@ -197,6 +217,38 @@ def main():
     }
     print(json.dumps(out))
     sim.close()
+
+
+def source_digest():
+    """SHA-256 over the kernel sources (csrc/*.hip, *.hpp, sorted by name)."""
+    d = os.path.join(ROOT, "paper_1912_00310_amd", "csrc")
+    h = hashlib.sha256()
+    for n in sorted(os.listdir(d)):
+        if n.endswith((".hip", ".hpp")):
+            with open(os.path.join(d, n), "rb") as f:
+                h.update(n.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(family, workload):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size),
+    or None when there is none or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"{family}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != source_digest():
+        return None
+    try:
+        return int(float(kv["hbm_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(wl, seconds):

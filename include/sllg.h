@@ -160,6 +160,10 @@ void sllg_free(sllg_ctx* ctx);
  * code 100000*plan + 1000*kernel shape + z planes per tile or slab. */
 int sllg_level_params(const sllg_ctx* ctx, int32_t level, double out[16]);
 
+/* Name of the kernel (template shape and tiling) that steps a level, as a
+ * NUL-terminated string of at most cap bytes. */
+int sllg_level_kernel(const sllg_ctx* ctx, int32_t level, char* name, int32_t cap);
+
 /* Current step index of a level. */
 int64_t sllg_level_step(const sllg_ctx* ctx, int32_t level);
 

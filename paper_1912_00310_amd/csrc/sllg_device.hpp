@@ -166,6 +166,17 @@ __device__ __forceinline__ V3 thermal_field(const LevelDev& L, uint64_t seed, ui
 // ---------------------------------------------------------------------------
 // Online loop accumulation for one instance at step n -> n+1 (FP64).
 // ---------------------------------------------------------------------------
+// Field where the ordinate crosses zero between steps (linear in H), and the
+// ordinate where the field crosses zero.
+__device__ inline double cross_field(double h0, double dH, double m0, double m1)
+{
+    return h0 - m0 * dH / (m1 - m0);
+}
+__device__ inline double zero_field_ordinate(double h0, double dH, double m0, double m1)
+{
+    return m0 + (m1 - m0) * (0.0 - h0) / dH;
+}
+
 // h0, h1: simulated field (Oe) at steps n and n + 1.
 __device__ inline void loop_accumulate_h(AccDev& a, const LevelDev& L, double h0, double h1, double m_new,
                                          double* rec)
@@ -178,21 +189,21 @@ __device__ inline void loop_accumulate_h(AccDev& a, const LevelDev& L, double h0
         a.ncross_d += change;
         if (!a.found_d && m0 > 0.0 && m_new <= 0.0) {
             a.found_d = 1;
-            a.hstar_d = h0 - m0 * dH / (m_new - m0);
+            a.hstar_d = cross_field(h0, dH, m0, m_new);
         }
         if (!a.found0_d && h0 > 0.0 && h1 <= 0.0) {
             a.found0_d = 1;
-            a.m0_d = m0 + (m_new - m0) * (0.0 - h0) / dH;
+            a.m0_d = zero_field_ordinate(h0, dH, m0, m_new);
         }
     } else if (dH > 0.0) {
         a.ncross_a += change;
         if (!a.found_a && m0 < 0.0 && m_new >= 0.0) {
             a.found_a = 1;
-            a.hstar_a = h0 - m0 * dH / (m_new - m0);
+            a.hstar_a = cross_field(h0, dH, m0, m_new);
         }
         if (!a.found0_a && h0 < 0.0 && h1 >= 0.0) {
             a.found0_a = 1;
-            a.m0_a = m0 + (m_new - m0) * (0.0 - h0) / dH;
+            a.m0_a = zero_field_ordinate(h0, dH, m0, m_new);
         }
     }
     a.m_prev = m_new;

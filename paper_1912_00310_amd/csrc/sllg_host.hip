@@ -1545,6 +1545,29 @@ int sllg_level_params(const sllg_ctx* C, int32_t level, double out[16])
     return SLLG_OK;
 }
 
+int sllg_level_kernel(const sllg_ctx* C, int32_t level, char* name, int32_t cap)
+{
+    if (!C || level < 0 || level >= (int)C->lv.size() || !name || cap <= 0) return fail(SLLG_E_INVAL, "bad args");
+    const LevelHost& h = C->lv[level];
+    char buf[96] = "none";
+    if (h.plan == kPlanStream) {
+        const Shape& sh = kShapes[h.shape];
+        if (sh.kind == 0)
+            snprintf(buf, sizeof(buf), "k_stream<%d,%d,%d> tz %d", sh.tx, sh.ty, sh.pz, h.tz);
+        else
+            snprintf(buf, sizeof(buf), "k_rows<%d,%d>", sh.tx, sh.ty);
+    } else if (h.plan == kPlanSlab) {
+        const SlabKernel& k = kSlabKernels[h.slab_kernel];
+        snprintf(buf, sizeof(buf), "k_slab<%d,%d> tz %d steps/launch %d", k.nt, k.k, h.slab_tz, kSlabChunk);
+    } else {
+        for (const auto& rs : C->res_sets)
+            if (std::find(rs.levels.begin(), rs.levels.end(), level) != rs.levels.end())
+                snprintf(buf, sizeof(buf), "k_resident<%d,%d>", rs.nw, rs.cpw);
+    }
+    snprintf(name, (size_t)cap, "%s", buf);
+    return SLLG_OK;
+}
+
 int64_t sllg_level_step(const sllg_ctx* C, int32_t level)
 {
     if (!C || level < 0 || level >= (int)C->lv.size()) return -1;

@@ -235,9 +235,13 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
 }
 
 // Fold the per-step slab partials of one launch into the loops, one block
-// per instance: first every thread sums the slabs of its steps in slab order
-// and evaluates the field, into LDS; then one lane runs the sequential FP64
-// loop accumulation over the launch's steps.
+// per instance, with no sequential pass over the steps: every thread sums
+// the slabs of its steps in slab order and evaluates the field (into LDS);
+// then each thread takes a contiguous run of steps and forms its part of the
+// area, its zero-crossing counts, its first crossings and its records; block
+// reductions combine them (area in a fixed order, so it is reproducible) and
+// thread 0 applies the first crossing of the launch with the same formulas
+// as the per-step accumulation.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_fold_slabs(const InstDev* __restrict__ insts, int inst0,
                                                    const int32_t* __restrict__ islab,
@@ -248,13 +252,19 @@ __global__ __launch_bounds__(NT) void k_fold_slabs(const InstDev* __restrict__ i
 {
     __shared__ double mz[kSlabChunk];
     __shared__ double hh[kSlabChunk + 1];
+    __shared__ double red[NT / 64];
+    __shared__ int cnt[2];
+    __shared__ int first[4];   // first falling crossing, rising crossing, falling H = 0, rising H = 0
     const int k = static_cast<int>(blockIdx.x);
     const int inst = inst0 + k;
+    const int tid = static_cast<int>(threadIdx.x);
     const InstDev I = insts[inst];
     const LevelDev& L = levels[I.level];
     const int s0 = islab[2 * k], ns = islab[2 * k + 1];   // level-relative first slab, count
     const double ncell = static_cast<double>(L.ncell);
-    for (int st = static_cast<int>(threadIdx.x); st <= nsteps; st += NT) {
+    if (tid < 4) first[tid] = INT_MAX;
+    if (tid < 2) cnt[tid] = 0;
+    for (int st = tid; st <= nsteps; st += NT) {
         hh[st] = L.hz_oe * wave_at(L, n0 + st);
         if (st == nsteps) continue;
         double v = 0.0;
@@ -262,10 +272,78 @@ __global__ __launch_bounds__(NT) void k_fold_slabs(const InstDev* __restrict__ i
         mz[st] = v / ncell;
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    AccDev a = accs[inst];
+    const AccDev a0 = accs[inst];
     double* rec = records + I.rec_off;
-    for (int st = 0; st < nsteps; ++st) loop_accumulate_h(a, L, hh[st], hh[st + 1], mz[st], rec);
+    const int per = (nsteps + NT - 1) / NT;
+    double area = 0.0;
+    int cd = 0, ca = 0;
+    int f[4] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX};
+    for (int st = tid * per; st < min(nsteps, (tid + 1) * per); ++st) {
+        const double m0 = st == 0 ? a0.m_prev : mz[st - 1], m1 = mz[st];
+        const double h0 = hh[st], h1 = hh[st + 1], dH = h1 - h0;
+        area += 0.5 * (m0 + m1) * dH;
+        const int change = (m0 > 0.0) != (m1 > 0.0);
+        if (dH < 0.0) {
+            cd += change;
+            if (m0 > 0.0 && m1 <= 0.0) f[0] = min(f[0], st);
+            if (h0 > 0.0 && h1 <= 0.0) f[2] = min(f[2], st);
+        } else if (dH > 0.0) {
+            ca += change;
+            if (m0 < 0.0 && m1 >= 0.0) f[1] = min(f[1], st);
+            if (h0 < 0.0 && h1 >= 0.0) f[3] = min(f[3], st);
+        }
+        const int q = a0.rec_phase + st + 1;
+        if (q % L.record_every == 0) {
+            const int64_t idx = a0.rec_idx + q / L.record_every;
+            if (idx < L.n_rec) rec[idx] = m1;
+        }
+    }
+    area = wave_sum_d(area);
+    if ((tid & 63) == 0) red[tid >> 6] = area;
+    if (cd) atomicAdd(&cnt[0], cd);
+    if (ca) atomicAdd(&cnt[1], ca);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (f[i] != INT_MAX) atomicMin(&first[i], f[i]);
+    __syncthreads();
+    if (tid != 0) return;
+    AccDev a = a0;
+    double tot = 0.0;
+    for (int w = 0; w < NT / 64; ++w) tot += red[w];
+    a.area -= tot;
+    a.ncross_d += cnt[0];
+    a.ncross_a += cnt[1];
+    auto at = [&](int st, double& m0, double& m1, double& h0, double& dH) {
+        m0 = st == 0 ? a0.m_prev : mz[st - 1];
+        m1 = mz[st];
+        h0 = hh[st];
+        dH = hh[st + 1] - h0;
+    };
+    double m0, m1, h0, dH;
+    if (!a.found_d && first[0] != INT_MAX) {
+        at(first[0], m0, m1, h0, dH);
+        a.found_d = 1;
+        a.hstar_d = cross_field(h0, dH, m0, m1);
+    }
+    if (!a.found_a && first[1] != INT_MAX) {
+        at(first[1], m0, m1, h0, dH);
+        a.found_a = 1;
+        a.hstar_a = cross_field(h0, dH, m0, m1);
+    }
+    if (!a.found0_d && first[2] != INT_MAX) {
+        at(first[2], m0, m1, h0, dH);
+        a.found0_d = 1;
+        a.m0_d = zero_field_ordinate(h0, dH, m0, m1);
+    }
+    if (!a.found0_a && first[3] != INT_MAX) {
+        at(first[3], m0, m1, h0, dH);
+        a.found0_a = 1;
+        a.m0_a = zero_field_ordinate(h0, dH, m0, m1);
+    }
+    if (nsteps > 0) a.m_prev = mz[nsteps - 1];
+    const int q = a0.rec_phase + nsteps;
+    a.rec_phase = q % L.record_every;
+    a.rec_idx = static_cast<int32_t>(min<int64_t>(a0.rec_idx + q / L.record_every, L.n_rec - 1));
     accs[inst] = a;
     if (!isfinite(a.m_prev)) atomicOr(status, 1);
 }

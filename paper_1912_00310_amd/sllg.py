@@ -84,6 +84,7 @@ def lib():
             "sllg_free": (None, [vp]),
             "sllg_level_params": (C.c_int, [vp, C.c_int32, P(C.c_double)]),
             "sllg_level_step": (C.c_int64, [vp, C.c_int32]),
+            "sllg_level_kernel": (C.c_int, [vp, C.c_int32, C.c_char_p, C.c_int32]),
             "sllg_get_state": (C.c_int, [vp, C.c_int32, C.c_int32, P(C.c_float)]),
             "sllg_set_state": (C.c_int, [vp, C.c_int32, C.c_int32, P(C.c_float)]),
             "sllg_set_plan": (C.c_int, [vp, C.c_int32, C.c_int32]),
@@ -106,7 +107,7 @@ def exported_symbols():
     return [n for n in (
         "sllg_workspace_bytes", "sllg_init", "sllg_run_sweep", "sllg_run_steps", "sllg_reset",
         "sllg_loop", "sllg_grad", "sllg_last_error", "sllg_free", "sllg_level_params",
-        "sllg_level_step", "sllg_get_state", "sllg_set_state", "sllg_set_plan",
+        "sllg_level_step", "sllg_level_kernel", "sllg_get_state", "sllg_set_state", "sllg_set_plan",
         "sllg_philox_probe", "sllg_get_axes", "sllg_set_timing", "sllg_kernel_time")]
 
 
@@ -223,6 +224,12 @@ class Sim:
         out = (C.c_double * 16)()
         _check("sllg_level_params", lib().sllg_level_params(self.ctx, level, out))
         return dict(zip(PARAM_KEYS, list(out)))
+
+    def kernel_name(self, level: int = 0) -> str:
+        """Kernel (template shape and tiling) that steps the level."""
+        buf = C.create_string_buffer(96)
+        _check("sllg_level_kernel", lib().sllg_level_kernel(self.ctx, level, buf, 96))
+        return buf.value.decode()
 
     def step(self, level: int = 0) -> int:
         return int(lib().sllg_level_step(self.ctx, level))

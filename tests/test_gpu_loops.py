@@ -87,10 +87,14 @@ def test_switching_loop_hc_and_area_within_two_sigma(P, orc):
     sim.close()
 
 
-def test_per_realization_accumulators_match_records(P):
-    # the online area (every step) equals the trapezoid over the full record
+@pytest.mark.parametrize("plan", ["auto", "slab"])
+def test_per_realization_accumulators_match_records(P, plan):
+    # the online area (every step) equals the trapezoid over the full record;
+    # the slab plan folds a launch's steps in parallel
     wl = switching_workload(4)
     sim = P.Sim(wl["material"], wl["levels"])
+    if plan == "slab":
+        sim.set_plan(0, P.PLAN_SLAB)
     sim.run_sweep()
     for r in range(4):
         H, m, st = sim.loop(0, r)
@@ -99,13 +103,19 @@ def test_per_realization_accumulators_match_records(P):
     sim.close()
 
 
-def test_decimated_records(P):
+@pytest.mark.parametrize("plan", ["auto", "slab"])
+def test_decimated_records(P, plan):
     wl = switching_workload(2)
     full = P.Sim(wl["material"], wl["levels"])
-    full.run_steps(5003)
     wl2 = switching_workload(2)
     wl2["levels"][0]["record_every"] = 10
     dec = P.Sim(wl2["material"], wl2["levels"])
+    if plan == "slab":
+        full.set_plan(0, P.PLAN_SLAB)
+        dec.set_plan(0, P.PLAN_SLAB)
+    # several slab launches, the last one partial
+    full.run_steps(3003)
+    full.run_steps(2000)
     dec.run_steps(5003)
     H1, m1, s1 = full.loop(0, 1)
     H2, m2, s2 = dec.loop(0, 1)
@@ -117,10 +127,11 @@ def test_decimated_records(P):
     dec.close()
 
 
-def test_plans_agree_on_full_loops(P):
+@pytest.mark.parametrize("other", ["stream", "slab"])
+def test_plans_agree_on_full_loops(P, other):
     wl = switching_workload(3)
     res = []
-    for plan in (P.PLAN_RESIDENT, P.PLAN_STREAM):
+    for plan in (P.PLAN_RESIDENT, P.PLAN_STREAM if other == "stream" else P.PLAN_SLAB):
         sim = P.Sim(wl["material"], wl["levels"])
         sim.set_plan(0, plan)
         sim.run_sweep()
@@ -130,7 +141,11 @@ def test_plans_agree_on_full_loops(P):
     # the ordinates differ only in how the FP32 partial sums of m_z are grouped
     # (64-lane waves vs tiles): at most a few FP32 ulps of the mean
     assert np.abs(res[0][1][1] - res[1][1][1]).max() < 1e-6
-    assert res[0][1][2]["Hc_sim"] == pytest.approx(res[1][1][2]["Hc_sim"], rel=1e-5)
+    st0, st1 = res[0][1][2], res[1][1][2]
+    assert st0["Hc_sim"] == pytest.approx(st1["Hc_sim"], rel=1e-5)
+    assert st0["S_sim"] == pytest.approx(st1["S_sim"], rel=1e-6)
+    assert st0["Mr_sim"] == pytest.approx(st1["Mr_sim"], abs=1e-6)
+    assert (st0["n_cross_desc"], st0["n_cross_asc"]) == (st1["n_cross_desc"], st1["n_cross_asc"])
 
 
 def test_multilevel_batch_each_level_matches_oracle(P, orc):
