@@ -104,11 +104,28 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
 
     const bool axes_on = L.has_axes != 0;
     const float* ax = axes + L.axes_off;
+    // The thermal field of a step does not depend on m: the field of step
+    // n + 1 is drawn while the boundary words of step n are in flight, and the
+    // applied field of step n + 1 is the end-of-step field of step n.
+    V3 hth[K];
+    auto draw = [&](int64_t n) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int e = r + j * NPP;
+            const int z = z0 - 1 + e;
+            if (!lane_on || e >= NE || z < 0 || z >= nz) continue;
+            hth[j] = thermal_field(L, I.seed, static_cast<uint32_t>(c + P * z), n);
+        }
+    };
+    draw(n0);
+    float hz1 = static_cast<float>(L.hz_amp * wave_at(L, n0));
+    // the last wave folds the block's m_z sum of the previous step
+    const bool folder = tid >= NT - 64;
     for (int st = 0; st < nsteps; ++st) {
         const int64_t n = n0 + st;
-        const float hz0 = static_cast<float>(L.hz_amp * wave_at(L, n));
-        const float hz1 = static_cast<float>(L.hz_amp * wave_at(L, n + 1));
-        V3 q[K], hth[K], u[K];
+        const float hz0 = hz1;
+        hz1 = static_cast<float>(L.hz_amp * wave_at(L, n + 1));
+        V3 q[K], u[K];
         // ---- 1. predictor on planes z0-1 .. z0+nzs
 #pragma unroll
         for (int j = 0; j < K; ++j) {
@@ -126,7 +143,6 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
                                  z < nz - 1 ? v3(mn(me + 1, 0), mn(me + 1, 1), mn(me + 1, 2)) : m);
             const int cell = c + P * z;
             u[j] = axes_on ? V3{ax[cell], ax[N + cell], ax[2 * N + cell]} : V3{L.ux, L.uy, L.uz};
-            hth[j] = thermal_field(L, I.seed, static_cast<uint32_t>(cell), n);
             V3 mp;
             heun_predict(L, m, ex, u[j], hz0, hth[j], mp, q[j]);
             float* o = Mp + e * 3 * P;
@@ -185,6 +201,7 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
             const float ws = wave_sum(msum);
             if ((tid & 63) == 0) red[tid >> 6] = static_cast<double>(ws);
         }
+        if (st + 1 < nsteps) draw(n + 1);
         // ---- 3. halo planes z0-2, z0-1 from the slab below, z0+nzs, z0+nzs+1
         //         from above, once every word carries this step's tag (bounded)
         for (int h = r; h < 4 && lane_on; h += NPP) {
@@ -217,7 +234,7 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
         }
         __syncthreads();
         if (s_abort) return;
-        if (tid == 0) {
+        if (folder && tid == NT - 64) {
             double tot = 0.0;
             for (int w = 0; w < NT / 64; ++w) tot += red[w];
             partials[static_cast<int64_t>(S.lid) * pstride + st] = tot;
