@@ -1132,6 +1132,27 @@ int tune_slab(sllg_ctx* C, int level, double* best_ms)
     }
     const int P = h.in.nx * h.in.ny;
     const int saved_plan = h.plan;
+    // SLLG_SLAB_SHAPE="kernel,tz" pins the slab kernel and thickness (profiling)
+    if (const char* f = getenv("SLLG_SLAB_SHAPE")) {
+        int ki = -1, tz = -1;
+        if (sscanf(f, "%d,%d", &ki, &tz) == 2 && ki >= 0 && ki < kNumSlabKernels && tz >= 2 && tz <= h.in.nz) {
+            h.plan = kPlanSlab;
+            h.slab_kernel = ki;
+            h.slab_tz = tz;
+            int rc = replan(C);
+            if (rc) return rc;
+            bool fits = false;
+            if (dispatch_slab(C, level, 0, 1, true, &fits) == hipSuccess && fits) {
+                g_tuned_slab[key] = std::make_tuple(ki, tz, 0.0);
+                *best_ms = 0.0;
+                h.plan = saved_plan;
+                return replan(C);
+            }
+            h.plan = saved_plan;
+            int rc2 = replan(C);
+            if (rc2) return rc2;
+        }
+    }
     const int tzs[] = {2, 3, 4, 5, 6, 8, 10, 12, 14, 16, 20, 24, 28, 32};
     hipEvent_t e0, e1;
     HIP_OK(hipEventCreate(&e0));
