@@ -185,6 +185,17 @@ int sllg_set_state(sllg_ctx* ctx, int32_t level, int32_t real, const float* host
  * co-resident, or a slab thicker than the workgroup's LDS holds). */
 int sllg_set_plan(sllg_ctx* ctx, int32_t level, int32_t plan);
 
+/* Slab plan (3) with a given kernel: kind 0 recomputes the halo predictor
+ * and exchanges two boundary planes per side once per step (slabs of at
+ * least 2 planes); kind 1 exchanges one boundary plane per side after each
+ * Heun stage (slabs of at least 1 plane).  threads and cells_per_thread
+ * name the instantiation, planes the slab thickness (the z extent is split
+ * into slabs of planes or planes + 1).  Both kinds give the same states as
+ * the other plans.  Returns SLLG_E_INVAL if no such kernel exists or it
+ * cannot hold the level; the previous plan is then kept. */
+int sllg_set_slab_shape(sllg_ctx* ctx, int32_t level, int32_t kind, int32_t threads, int32_t cells_per_thread,
+                        int32_t planes);
+
 /* Device Philox4x32-10 of the thermal-noise stream: for k < n, the four raw
  * words for (seed, level, tag, cells[k], steps[k]) and the three normals the
  * kernels derive from them.  d_scratch: >= 40*n bytes of device memory.

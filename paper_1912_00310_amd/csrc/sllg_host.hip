@@ -84,10 +84,16 @@ struct LevelHost {
     int64_t step;         // host view of the step index
 };
 
+// Slab kernels.  kind 0: k_slab<nt, k> (halo predictor recomputed, one
+// exchange per step, slabs of >= 2 planes); kind 1: k_slab2<nt, k> (m' and
+// m_{n+1} exchanged, slabs of >= 1 plane).
 struct SlabKernel {
-    int nt, k;
+    int kind, nt, k;
 };
-const SlabKernel kSlabKernels[] = {{192, 4}, {384, 2}, {384, 3}, {576, 2}, {768, 1}, {768, 2}, {1024, 1}, {1024, 2}};
+const SlabKernel kSlabKernels[] = {{0, 192, 4},  {0, 384, 2},  {0, 384, 3},  {0, 576, 2},  {0, 768, 1},
+                                   {0, 768, 2},  {0, 1024, 1}, {0, 1024, 2}, {1, 192, 2},  {1, 384, 1},
+                                   {1, 576, 1},  {1, 768, 1},  {1, 1024, 1}, {1, 384, 2},  {1, 768, 2},
+                                   {1, 1024, 2}};
 constexpr int kNumSlabKernels = sizeof(kSlabKernels) / sizeof(kSlabKernels[0]);
 
 bool slab_eligible(const sllg_level& L) { return L.nx * L.ny <= 1024 && L.nz >= 4; }
@@ -366,7 +372,7 @@ Layout make_layout(const sllg_material& m, const std::vector<LevelHost>& lv, int
         tiles += max_tiles_for(h.in) * h.in.n_real;
         chunks += ceil_div(h.ncell, 64) * h.in.n_real;
         if (slab_eligible(h.in)) {
-            const int64_t ns = (int64_t)(h.in.nz / 2) * h.in.n_real;
+            const int64_t ns = (int64_t)h.in.nz * h.in.n_real;   // one-plane slabs at most
             L.max_slabs += ns;
             L.xch_words += 2 * ns * 12 * (int64_t)h.in.nx * h.in.ny;
         }
@@ -615,14 +621,21 @@ int upload_tables(sllg_ctx* C)
 // exchanges then stay within one XCD.  The order only affects speed.
 constexpr int kXcds = 8;
 
+// Slabs per instance: ceil(nz / tz), but never a slab thinner than the kernel
+// allows (two planes for kind 0, one for kind 1); every slab then has at most
+// tz + 1 planes.
+int slab_count(const LevelHost& h)
+{
+    const int minp = kSlabKernels[h.slab_kernel].kind == 0 ? 2 : 1;
+    const int tz = std::max(minp, h.slab_tz);
+    return std::max(1, std::min((h.in.nz + tz - 1) / tz, h.in.nz / minp));
+}
+
 void build_slabs(sllg_ctx* C, LevelHost& h)
 {
     h.slab0 = (int)C->h_slabs.size();
     const int nz = h.in.nz;
-    const int tz = std::max(2, h.slab_tz);
-    // ceil(nz / tz) slabs, but never a slab thinner than two planes: every
-    // slab then has at most tz + 1 planes
-    const int nsl = std::max(1, std::min((nz + tz - 1) / tz, nz / 2));
+    const int nsl = slab_count(h);
     const int base = nz / nsl, extra = nz % nsl;
     const int total = nsl * h.ninst;
     // lid = r * nsl + k  ->  block index
@@ -779,32 +792,45 @@ hipError_t dispatch_stream(sllg_ctx* C, int level)
 // ---------------------------------------------------------------------------
 int slab_max_planes(const LevelHost& h)
 {
-    const int tz = std::max(2, h.slab_tz);
-    const int nsl = std::max(1, std::min((h.in.nz + tz - 1) / tz, h.in.nz / 2));
+    const int nsl = slab_count(h);
     return h.in.nz / nsl + (h.in.nz % nsl ? 1 : 0);
 }
 
 size_t slab_lds(const LevelHost& h)
 {
-    return sizeof(float) * (size_t)(2 * slab_max_planes(h) + 6) * 3 * h.in.nx * h.in.ny;
+    const int mp = slab_max_planes(h);
+    const int planes = kSlabKernels[h.slab_kernel].kind == 0 ? 2 * mp + 6 : 2 * mp + 4;
+    return sizeof(float) * (size_t)planes * 3 * h.in.nx * h.in.ny;
 }
 
-template <int NT, int K>
+template <int KIND, int NT, int K>
 hipError_t launch_slab_t(sllg_ctx* C, int level, int64_t n0, int ns, bool check_only, bool* fits)
 {
     const LevelHost& h = C->lv[level];
-    // every predicted plane (slab + 2 halo planes) must have a thread slot
-    if (slab_max_planes(h) + 2 > K * (NT / (h.in.nx * h.in.ny))) {
+    // every computed plane must have a thread slot (kind 0: slab + 2 halo planes)
+    if (slab_max_planes(h) + (KIND == 0 ? 2 : 0) > K * (NT / (h.in.nx * h.in.ny))) {
         if (fits) *fits = false;
         return check_only ? hipSuccess : hipErrorInvalidConfiguration;
     }
     const size_t lds = slab_lds(h);
-    const void* fn = reinterpret_cast<const void*>(&k_slab<NT, K>);
+    const void* fn = KIND == 0 ? reinterpret_cast<const void*>(&k_slab<NT, K>)
+                               : reinterpret_cast<const void*>(&k_slab2<NT, K>);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     int nb = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, NT, lds);
     if (e != hipSuccess) return e;
+    // Every workgroup waits on its neighbours, so all must be resident.  The
+    // occupancy query assumes a workgroup's waves spread evenly over the four
+    // SIMDs; bound it by the wave slots of the fullest SIMD instead (a
+    // workgroup may put ceil(waves / 4) waves on one SIMD).
+    hipFuncAttributes fa{};
+    e = hipFuncGetAttributes(&fa, fn);
+    if (e != hipSuccess) return e;
+    const int vgpr = std::max(8, (fa.numRegs + 7) / 8 * 8);
+    const int per_simd = std::min(8, 512 / vgpr);
+    const int waves = NT / 64;
+    nb = std::min(nb, per_simd / ((waves + 3) / 4));
     if (fits) *fits = (int64_t)nb * C->num_cus >= h.nslab && nb > 0;
     if (check_only) return hipSuccess;
     if ((int64_t)nb * C->num_cus < h.nslab) return hipErrorCooperativeLaunchTooLarge;
@@ -837,15 +863,23 @@ hipError_t dispatch_slab(sllg_ctx* C, int level, int64_t n0, int ns, bool check_
                          bool* fits = nullptr)
 {
     const SlabKernel k = kSlabKernels[C->lv[level].slab_kernel];
-    switch (k.nt * 10 + k.k) {
-    case 1924: return launch_slab_t<192, 4>(C, level, n0, ns, check_only, fits);
-    case 3842: return launch_slab_t<384, 2>(C, level, n0, ns, check_only, fits);
-    case 3843: return launch_slab_t<384, 3>(C, level, n0, ns, check_only, fits);
-    case 5762: return launch_slab_t<576, 2>(C, level, n0, ns, check_only, fits);
-    case 7681: return launch_slab_t<768, 1>(C, level, n0, ns, check_only, fits);
-    case 7682: return launch_slab_t<768, 2>(C, level, n0, ns, check_only, fits);
-    case 10241: return launch_slab_t<1024, 1>(C, level, n0, ns, check_only, fits);
-    case 10242: return launch_slab_t<1024, 2>(C, level, n0, ns, check_only, fits);
+    switch (k.kind * 100000 + k.nt * 10 + k.k) {
+    case 1924: return launch_slab_t<0, 192, 4>(C, level, n0, ns, check_only, fits);
+    case 3842: return launch_slab_t<0, 384, 2>(C, level, n0, ns, check_only, fits);
+    case 3843: return launch_slab_t<0, 384, 3>(C, level, n0, ns, check_only, fits);
+    case 5762: return launch_slab_t<0, 576, 2>(C, level, n0, ns, check_only, fits);
+    case 7681: return launch_slab_t<0, 768, 1>(C, level, n0, ns, check_only, fits);
+    case 7682: return launch_slab_t<0, 768, 2>(C, level, n0, ns, check_only, fits);
+    case 10241: return launch_slab_t<0, 1024, 1>(C, level, n0, ns, check_only, fits);
+    case 10242: return launch_slab_t<0, 1024, 2>(C, level, n0, ns, check_only, fits);
+    case 101922: return launch_slab_t<1, 192, 2>(C, level, n0, ns, check_only, fits);
+    case 103841: return launch_slab_t<1, 384, 1>(C, level, n0, ns, check_only, fits);
+    case 105761: return launch_slab_t<1, 576, 1>(C, level, n0, ns, check_only, fits);
+    case 107681: return launch_slab_t<1, 768, 1>(C, level, n0, ns, check_only, fits);
+    case 110241: return launch_slab_t<1, 1024, 1>(C, level, n0, ns, check_only, fits);
+    case 103842: return launch_slab_t<1, 384, 2>(C, level, n0, ns, check_only, fits);
+    case 107682: return launch_slab_t<1, 768, 2>(C, level, n0, ns, check_only, fits);
+    case 110242: return launch_slab_t<1, 1024, 2>(C, level, n0, ns, check_only, fits);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1135,7 +1169,7 @@ int tune_slab(sllg_ctx* C, int level, double* best_ms)
     // SLLG_SLAB_SHAPE="kernel,tz" pins the slab kernel and thickness (profiling)
     if (const char* f = getenv("SLLG_SLAB_SHAPE")) {
         int ki = -1, tz = -1;
-        if (sscanf(f, "%d,%d", &ki, &tz) == 2 && ki >= 0 && ki < kNumSlabKernels && tz >= 2 && tz <= h.in.nz) {
+        if (sscanf(f, "%d,%d", &ki, &tz) == 2 && ki >= 0 && ki < kNumSlabKernels && tz >= 1 && tz <= h.in.nz) {
             h.plan = kPlanSlab;
             h.slab_kernel = ki;
             h.slab_tz = tz;
@@ -1153,7 +1187,7 @@ int tune_slab(sllg_ctx* C, int level, double* best_ms)
             if (rc2) return rc2;
         }
     }
-    const int tzs[] = {2, 3, 4, 5, 6, 8, 10, 12, 14, 16, 20, 24, 28, 32};
+    const int tzs[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 14, 16, 20, 24, 28, 32};
     hipEvent_t e0, e1;
     HIP_OK(hipEventCreate(&e0));
     HIP_OK(hipEventCreate(&e1));
@@ -1162,9 +1196,11 @@ int tune_slab(sllg_ctx* C, int level, double* best_ms)
         const int NPP = kSlabKernels[ki].nt / P;
         if (NPP < 1) continue;
         const int cap = kSlabKernels[ki].k * NPP;
+        const int halo = kSlabKernels[ki].kind == 0 ? 2 : 0;   // recomputed planes
+        const int minp = kSlabKernels[ki].kind == 0 ? 2 : 1;
         for (int tz : tzs) {
-            if (tz + 3 > cap || tz > h.in.nz) continue;
-            if ((kSlabKernels[ki].k - 1) * NPP >= tz + 3) continue;   // an idle cell slot per thread
+            if (tz < minp || tz + 1 + halo > cap || tz > h.in.nz) continue;
+            if ((kSlabKernels[ki].k - 1) * NPP >= tz + 1 + halo) continue;   // an idle cell slot per thread
             h.plan = kPlanSlab;
             h.slab_kernel = ki;
             h.slab_tz = tz;
@@ -1579,7 +1615,8 @@ int sllg_level_kernel(const sllg_ctx* C, int32_t level, char* name, int32_t cap)
             snprintf(buf, sizeof(buf), "k_rows<%d,%d>", sh.tx, sh.ty);
     } else if (h.plan == kPlanSlab) {
         const SlabKernel& k = kSlabKernels[h.slab_kernel];
-        snprintf(buf, sizeof(buf), "k_slab<%d,%d> tz %d steps/launch %d", k.nt, k.k, h.slab_tz, kSlabChunk);
+        snprintf(buf, sizeof(buf), "%s<%d,%d> tz %d steps/launch %d", k.kind == 0 ? "k_slab" : "k_slab2", k.nt, k.k,
+                 h.slab_tz, kSlabChunk);
     } else {
         for (const auto& rs : C->res_sets)
             if (std::find(rs.levels.begin(), rs.levels.end(), level) != rs.levels.end())
@@ -1654,7 +1691,8 @@ int sllg_set_plan(sllg_ctx* C, int32_t level, int32_t plan)
             const int P = h.in.nx * h.in.ny;
             h.slab_kernel = -1;
             for (int ki = 0; ki < kNumSlabKernels && h.slab_kernel < 0; ++ki)
-                if (kSlabKernels[ki].nt / P >= 1 && kSlabKernels[ki].k * (kSlabKernels[ki].nt / P) >= 5) {
+                if (kSlabKernels[ki].kind == 0 && kSlabKernels[ki].nt / P >= 1 &&
+                    kSlabKernels[ki].k * (kSlabKernels[ki].nt / P) >= 5) {
                     h.slab_kernel = ki;
                     h.slab_tz = 2;
                 }
@@ -1681,6 +1719,38 @@ int sllg_set_plan(sllg_ctx* C, int32_t level, int32_t plan)
         HIP_OK(hipMemcpyAsync(C->d_steps + l, &C->lv[l].step, sizeof(int64_t), hipMemcpyHostToDevice,
                               C->stream));
     HIP_OK(hipStreamSynchronize(C->stream));
+    return SLLG_OK;
+}
+
+int sllg_set_slab_shape(sllg_ctx* C, int32_t level, int32_t kind, int32_t threads, int32_t cells_per_thread,
+                        int32_t planes)
+{
+    if (!C || level < 0 || level >= (int)C->lv.size()) return fail(SLLG_E_INVAL, "bad level");
+    LevelHost& h = C->lv[level];
+    if (!slab_eligible(h.in)) return fail(SLLG_E_INVAL, "level %d cannot use slabs (nx*ny <= 1024, nz >= 4)", level);
+    int ki = -1;
+    for (int i = 0; i < kNumSlabKernels; ++i)
+        if (kSlabKernels[i].kind == kind && kSlabKernels[i].nt == threads && kSlabKernels[i].k == cells_per_thread)
+            ki = i;
+    if (ki < 0) return fail(SLLG_E_INVAL, "no slab kernel kind %d <%d,%d>", kind, threads, cells_per_thread);
+    if (planes < (kind == 0 ? 2 : 1) || planes > h.in.nz) return fail(SLLG_E_INVAL, "bad slab thickness %d", planes);
+    const int saved[4] = {h.plan, h.slab_kernel, h.slab_tz, h.forced};
+    h.plan = kPlanSlab;
+    h.slab_kernel = ki;
+    h.slab_tz = planes;
+    h.forced = 1;
+    int rc = replan(C);
+    bool fits = false;
+    if (!rc && (dispatch_slab(C, level, 0, 1, true, &fits) != hipSuccess || !fits)) rc = SLLG_E_INVAL;
+    if (rc) {
+        h.plan = saved[0];
+        h.slab_kernel = saved[1];
+        h.slab_tz = saved[2];
+        h.forced = saved[3];
+        (void)replan(C);
+        return fail(SLLG_E_INVAL, "slab kernel kind %d <%d,%d> with %d planes cannot hold level %d", kind, threads,
+                    cells_per_thread, planes, level);
+    }
     return SLLG_OK;
 }
 

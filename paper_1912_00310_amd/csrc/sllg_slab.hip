@@ -251,6 +251,217 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
     }
 }
 
+// Slab variant without recomputation: the predictor runs on the slab's own
+// planes only and the boundary planes of m' are exchanged as well, so a step
+// has two trips through device memory (m' after the predictor, m_{n+1} after
+// the corrector), each of one plane per side, and half the per-cell work of
+// k_slab.  A slab may be a single plane.  Rows of threads without own planes
+// poll the neighbours' words while the other rows compute.  One buffer per
+// stage suffices: a workgroup writes a stage's slot again only after it has
+// received the neighbour's words of the other stage, which the neighbour
+// publishes after it has read the slot.
+template <int NT, int K>
+__global__ __launch_bounds__(NT) void k_slab2(const SlabDev* __restrict__ slabs, const InstDev* __restrict__ insts,
+                                              const LevelDev* __restrict__ levels, float* __restrict__ buf0,
+                                              float* __restrict__ buf1, const float* __restrict__ axes,
+                                              uint64_t* __restrict__ xch, uint32_t tag_base,
+                                              double* __restrict__ partials, int pstride, float* __restrict__ ckpt,
+                                              int ckpt_every, int64_t n0, int nsteps, int* __restrict__ status)
+{
+    extern __shared__ float lds[];
+    __shared__ double red[NT / 64];
+    __shared__ int s_abort;
+
+    const int sid = static_cast<int>(blockIdx.x);
+    const SlabDev S = slabs[sid];
+    const InstDev I = insts[S.inst];
+    const LevelDev& L = levels[I.level];
+    const int nx = L.nx, ny = L.ny, nz = L.nz, N = L.ncell;
+    const int P = nx * ny;
+    const int NPP = NT / P;
+    const int tid = threadIdx.x;
+    const int c = tid % P, r = tid / P;
+    const bool lane_on = r < NPP;
+    const int x = c % nx, y = c / nx;
+    const int z0 = S.z0, nzs = S.nzs;
+    // planes me = 0 .. nzs + 1 hold z0 - 1 .. z0 + nzs (halo, own planes, halo)
+    float* Mn = lds;                            // m_n
+    float* Mp = lds + (nzs + 2) * 3 * P;        // m'
+    const int ixm = x > 0 ? c - 1 : c, ixp = x < nx - 1 ? c + 1 : c;
+    const int iym = y > 0 ? c - nx : c, iyp = y < ny - 1 ? c + nx : c;
+    // exchange slot (3 x P words): stage 0 = m', 1 = m_{n+1}; slot 0 = first own plane, 1 = last
+    auto xslot = [&](int stage, int slab, int slot) {
+        return xch + ((static_cast<int64_t>(stage) * gridDim.x + slab) * 2 + slot) * 3 * P;
+    };
+    // rows that poll the halo below (h = 0) and above (h = 1)
+    const int prow0 = nzs % NPP, prow1 = (nzs + 1) % NPP;
+    if (tid == 0) s_abort = 0;
+
+    {
+        const float* mi = ((n0 & 1) ? buf1 : buf0) + I.state_off;
+        for (int me = r; me < nzs + 2; me += NPP) {
+            const int z = z0 - 1 + me;
+            if (!lane_on || z < 0 || z >= nz) continue;
+            const int cell = c + P * z;
+            Mn[(me * 3 + 0) * P + c] = mi[cell];
+            Mn[(me * 3 + 1) * P + c] = mi[N + cell];
+            Mn[(me * 3 + 2) * P + c] = mi[2 * N + cell];
+        }
+    }
+    __syncthreads();
+
+    const bool axes_on = L.has_axes != 0;
+    const float* ax = axes + L.axes_off;
+    V3 hth[K];
+    auto draw = [&](int64_t n) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int e = r + j * NPP;
+            if (!lane_on || e >= nzs) continue;
+            hth[j] = thermal_field(L, I.seed, static_cast<uint32_t>(c + P * (z0 + e)), n);
+        }
+    };
+    // receive one halo plane of a stage into dst (bounded wait); false on timeout
+    auto receive = [&](int stage, int h, float* dst, uint32_t tag) -> bool {
+        const int nb = h == 0 ? S.prev : S.next;
+        if (nb < 0) return true;
+        const uint64_t* src = xslot(stage, nb, h == 0 ? 1 : 0);
+        uint64_t w0, w1, w2;
+        uint32_t spins = 0;
+        for (;;) {
+            w0 = ld_word(src + c);
+            w1 = ld_word(src + P + c);
+            w2 = ld_word(src + 2 * P + c);
+            if (word_tag(w0) == tag && word_tag(w1) == tag && word_tag(w2) == tag) break;
+            if (++spins > kSlabSpinLimit) return false;
+            __builtin_amdgcn_s_sleep(1);
+        }
+        dst[c] = word_val(w0);
+        dst[P + c] = word_val(w1);
+        dst[2 * P + c] = word_val(w2);
+        return true;
+    };
+    auto fail = [&]() {
+        s_abort = 1;
+        atomicOr(status, 2);
+    };
+    draw(n0);
+    float hz1 = static_cast<float>(L.hz_amp * wave_at(L, n0));
+    const bool folder = tid >= NT - 64;
+    for (int st = 0; st < nsteps; ++st) {
+        const int64_t n = n0 + st;
+        const float hz0 = hz1;
+        hz1 = static_cast<float>(L.hz_amp * wave_at(L, n + 1));
+        const uint32_t tag = tag_base + static_cast<uint32_t>(st) + 1u;
+        V3 q[K], u[K];
+        // ---- 1. predictor on own planes; boundary planes of m' go out
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int e = r + j * NPP;
+            if (!lane_on || e >= nzs) continue;
+            const int z = z0 + e, me = e + 1;
+            const float* pl = Mn + me * 3 * P;
+            const V3 m = v3(pl[c], pl[P + c], pl[2 * P + c]);
+            const float* plm = pl - 3 * P;
+            const float* plp = pl + 3 * P;
+            const V3 ex = nb_sum(m, v3(pl[ixm], pl[P + ixm], pl[2 * P + ixm]),
+                                 v3(pl[ixp], pl[P + ixp], pl[2 * P + ixp]),
+                                 v3(pl[iym], pl[P + iym], pl[2 * P + iym]),
+                                 v3(pl[iyp], pl[P + iyp], pl[2 * P + iyp]),
+                                 z > 0 ? v3(plm[c], plm[P + c], plm[2 * P + c]) : m,
+                                 z < nz - 1 ? v3(plp[c], plp[P + c], plp[2 * P + c]) : m);
+            const int cell = c + P * z;
+            u[j] = axes_on ? V3{ax[cell], ax[N + cell], ax[2 * N + cell]} : V3{L.ux, L.uy, L.uz};
+            V3 mp;
+            heun_predict(L, m, ex, u[j], hz0, hth[j], mp, q[j]);
+            float* o = Mp + me * 3 * P;
+            o[c] = mp.x;
+            o[P + c] = mp.y;
+            o[2 * P + c] = mp.z;
+            if (e == 0) {
+                uint64_t* d = xslot(0, sid, 0);
+                st_word(d + c, mp.x, tag);
+                st_word(d + P + c, mp.y, tag);
+                st_word(d + 2 * P + c, mp.z, tag);
+            }
+            if (e == nzs - 1) {
+                uint64_t* d = xslot(0, sid, 1);
+                st_word(d + c, mp.x, tag);
+                st_word(d + P + c, mp.y, tag);
+                st_word(d + 2 * P + c, mp.z, tag);
+            }
+            if (ckpt != nullptr && ckpt_every > 0 && (n % ckpt_every) == 0) {
+                float* cp = ckpt + I.ckpt_off + (n / ckpt_every) * 3 * static_cast<int64_t>(N);
+                cp[cell] = m.x;
+                cp[N + cell] = m.y;
+                cp[2 * N + cell] = m.z;
+            }
+        }
+        if (lane_on && r == prow0 && !receive(0, 0, Mp, tag)) fail();
+        if (lane_on && r == prow1 && !receive(0, 1, Mp + (nzs + 1) * 3 * P, tag)) fail();
+        __syncthreads();
+        if (s_abort) return;
+        // ---- 2. corrector on own planes; boundary planes of m_{n+1} go out
+        float msum = 0.0f;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int e = r + j * NPP;
+            if (!lane_on || e >= nzs) continue;
+            const int z = z0 + e, me = e + 1;
+            const float* pl = Mp + me * 3 * P;
+            const V3 mp = v3(pl[c], pl[P + c], pl[2 * P + c]);
+            const float* plm = pl - 3 * P;
+            const float* plp = pl + 3 * P;
+            const V3 ex = nb_sum(mp, v3(pl[ixm], pl[P + ixm], pl[2 * P + ixm]),
+                                 v3(pl[ixp], pl[P + ixp], pl[2 * P + ixp]),
+                                 v3(pl[iym], pl[P + iym], pl[2 * P + iym]),
+                                 v3(pl[iyp], pl[P + iyp], pl[2 * P + iyp]),
+                                 z > 0 ? v3(plm[c], plm[P + c], plm[2 * P + c]) : mp,
+                                 z < nz - 1 ? v3(plp[c], plp[P + c], plp[2 * P + c]) : mp);
+            const V3 mnew = heun_correct(L, mp, ex, u[j], hz1, hth[j], q[j]);
+            float* o = Mn + me * 3 * P;
+            o[c] = mnew.x;
+            o[P + c] = mnew.y;
+            o[2 * P + c] = mnew.z;
+            msum += mnew.z;
+            if (e == 0) {
+                uint64_t* d = xslot(1, sid, 0);
+                st_word(d + c, mnew.x, tag);
+                st_word(d + P + c, mnew.y, tag);
+                st_word(d + 2 * P + c, mnew.z, tag);
+            }
+            if (e == nzs - 1) {
+                uint64_t* d = xslot(1, sid, 1);
+                st_word(d + c, mnew.x, tag);
+                st_word(d + P + c, mnew.y, tag);
+                st_word(d + 2 * P + c, mnew.z, tag);
+            }
+        }
+        {
+            const float ws = wave_sum(msum);
+            if ((tid & 63) == 0) red[tid >> 6] = static_cast<double>(ws);
+        }
+        if (st + 1 < nsteps) draw(n + 1);
+        if (lane_on && r == prow0 && !receive(1, 0, Mn, tag)) fail();
+        if (lane_on && r == prow1 && !receive(1, 1, Mn + (nzs + 1) * 3 * P, tag)) fail();
+        __syncthreads();
+        if (s_abort) return;
+        if (folder && tid == NT - 64) {
+            double tot = 0.0;
+            for (int w = 0; w < NT / 64; ++w) tot += red[w];
+            partials[static_cast<int64_t>(S.lid) * pstride + st] = tot;
+        }
+    }
+    float* mo = (((n0 + nsteps) & 1) ? buf1 : buf0) + I.state_off;
+    for (int me = 1 + r; me <= nzs; me += NPP) {
+        if (!lane_on) break;
+        const int cell = c + P * (z0 - 1 + me);
+        mo[cell] = Mn[(me * 3 + 0) * P + c];
+        mo[N + cell] = Mn[(me * 3 + 1) * P + c];
+        mo[2 * N + cell] = Mn[(me * 3 + 2) * P + c];
+    }
+}
+
 // Fold the per-step slab partials of one launch into the loops, one block
 // per instance, with no sequential pass over the steps: every thread sums
 // the slabs of its steps in slab order and evaluates the field (into LDS);

@@ -88,6 +88,7 @@ def lib():
             "sllg_get_state": (C.c_int, [vp, C.c_int32, C.c_int32, P(C.c_float)]),
             "sllg_set_state": (C.c_int, [vp, C.c_int32, C.c_int32, P(C.c_float)]),
             "sllg_set_plan": (C.c_int, [vp, C.c_int32, C.c_int32]),
+            "sllg_set_slab_shape": (C.c_int, [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
             "sllg_philox_probe": (C.c_int, [C.c_uint64, C.c_uint32, C.c_uint32, P(C.c_uint32),
                                             P(C.c_uint64), C.c_int32, P(C.c_uint32), P(C.c_float), vp, vp]),
             "sllg_get_axes": (C.c_int, [vp, C.c_int32, P(C.c_float)]),
@@ -108,6 +109,7 @@ def exported_symbols():
         "sllg_workspace_bytes", "sllg_init", "sllg_run_sweep", "sllg_run_steps", "sllg_reset",
         "sllg_loop", "sllg_grad", "sllg_last_error", "sllg_free", "sllg_level_params",
         "sllg_level_step", "sllg_level_kernel", "sllg_get_state", "sllg_set_state", "sllg_set_plan",
+        "sllg_set_slab_shape",
         "sllg_philox_probe", "sllg_get_axes", "sllg_set_timing", "sllg_kernel_time")]
 
 
@@ -252,6 +254,11 @@ class Sim:
 
     def set_plan(self, level: int, plan: int):
         _check("sllg_set_plan", lib().sllg_set_plan(self.ctx, level, plan))
+
+    def set_slab_shape(self, level: int, kind: int, threads: int, cells_per_thread: int, planes: int):
+        """Slab plan with a given kernel (kind 0: halo recompute, 1: m' exchange) and thickness."""
+        _check("sllg_set_slab_shape", lib().sllg_set_slab_shape(self.ctx, level, kind, threads,
+                                                                cells_per_thread, planes))
 
     def axes(self, level: int = 0) -> np.ndarray:
         out = np.zeros(3 * self.ncell(level), dtype=np.float32)

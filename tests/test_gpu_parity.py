@@ -173,13 +173,30 @@ def test_realizations_are_independent_streams(P, orc):
 
 
 
-def test_slab_plan_matches_oracle_and_other_plans(P, orc):
+# (kind, threads, cells per thread, planes): kind 0 recomputes the halo
+# predictor, kind 1 exchanges m' as well; None = the plan's default kernel
+SLAB_SHAPES = [None, (0, 1024, 1, 2), (1, 1024, 1, 2), (1, 1024, 1, 1), (1, 384, 1, 2), (1, 192, 2, 2),
+               (1, 768, 2, 3)]
+
+
+def set_slab(P, sim, shape):
+    if shape is None:
+        sim.set_plan(0, P.PLAN_SLAB)
+    else:
+        sim.set_slab_shape(0, *shape)
+
+
+@pytest.mark.parametrize("shape", SLAB_SHAPES)
+def test_slab_plan_matches_oracle_and_other_plans(P, orc, shape):
     wl = W.workload("rod_b1_ens8")
     wl["levels"][0]["n_real"] = 2
     out = {}
     for plan in (P.PLAN_STREAM, P.PLAN_SLAB):
         sim = P.Sim(wl["material"], wl["levels"])
-        sim.set_plan(0, plan)
+        if plan == P.PLAN_SLAB:
+            set_slab(P, sim, shape)
+        else:
+            sim.set_plan(0, plan)
         sim.run_steps(300)
         out[plan] = (sim.get_state(0, 1), sim.loop(0, 1)[1])
         sim.close()
@@ -192,14 +209,15 @@ def test_slab_plan_matches_oracle_and_other_plans(P, orc):
     assert np.abs(out[P.PLAN_SLAB][1] - mb).max() < 2e-6
 
 
+@pytest.mark.parametrize("shape", [None, (1, 192, 2, 1), (1, 1024, 1, 2)])
 @pytest.mark.parametrize("dims", [(5, 7, 11), (8, 24, 5), (3, 2, 4)])
-def test_slab_plan_ragged(P, orc, dims):
+def test_slab_plan_ragged(P, orc, dims, shape):
     wl = W.workload("block_b2_cone10")
     wl["levels"][0].update(nx=dims[0], ny=dims[1], nz=dims[2], n_real=2)
     wl["material"]["sweep_Oe_per_ns"] = 1e5
     lv = oracle_level(wl)
     sim = P.Sim(wl["material"], wl["levels"])
-    sim.set_plan(0, P.PLAN_SLAB)
+    set_slab(P, sim, shape)
     u = orc.make_axes(lv)
     N = lv["nx"] * lv["ny"] * lv["nz"]
     m_ref = [np.tile([0.0, 0.0, 1.0], (N, 1)) for _ in range(2)]
@@ -211,7 +229,8 @@ def test_slab_plan_ragged(P, orc, dims):
     sim.close()
 
 
-def test_slab_plan_chunks_and_checkpoints(P):
+@pytest.mark.parametrize("shape", [None, (1, 192, 2, 1)])
+def test_slab_plan_chunks_and_checkpoints(P, shape):
     # more steps than one slab launch holds, checkpoints written by the slab kernel
     wl = W.workload("rod_b4_adjoint64")
     wl["material"]["sweep_Oe_per_ns"] *= 20          # 2000 steps
@@ -219,7 +238,10 @@ def test_slab_plan_chunks_and_checkpoints(P):
     res = {}
     for plan in (P.PLAN_RESIDENT, P.PLAN_SLAB):
         sim = P.Sim(wl["material"], wl["levels"], ckpt_every=256)
-        sim.set_plan(0, plan)
+        if plan == P.PLAN_SLAB:
+            set_slab(P, sim, shape)
+        else:
+            sim.set_plan(0, plan)
         sim.run_sweep()
         res[plan] = (sim.get_state(0, 1), sim.grad(0))
         sim.close()
