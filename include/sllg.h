@@ -196,6 +196,15 @@ int sllg_set_plan(sllg_ctx* ctx, int32_t level, int32_t plan);
 int sllg_set_slab_shape(sllg_ctx* ctx, int32_t level, int32_t kind, int32_t threads, int32_t cells_per_thread,
                         int32_t planes);
 
+/* Streamed plan (2) with a given tile kernel and z planes per tile: kind 0
+ * = x-y window (a, b threads, c z planes per thread block), kind 1 = full-width
+ * rows with an LDS ring of m_n planes (a threads, b cells per thread, c = 1),
+ * kind 2 = full-width rows with the z-columns in registers (a threads, b
+ * cells per thread, c = 1).  All kernels give the same states.  Returns
+ * SLLG_E_INVAL if no such kernel exists or the tiling does not fit. */
+int sllg_set_stream_shape(sllg_ctx* ctx, int32_t level, int32_t kind, int32_t a, int32_t b, int32_t c,
+                          int32_t planes);
+
 /* Device Philox4x32-10 of the thermal-noise stream: for k < n, the four raw
  * words for (seed, level, tag, cells[k], steps[k]) and the three normals the
  * kernels derive from them.  d_scratch: >= 40*n bytes of device memory.

@@ -26,6 +26,7 @@
 #include "sllg_rows.hip"
 #include "sllg_adjoint.hip"
 #include "sllg_slab.hip"
+#include "sllg_rows2.hip"
 
 using namespace sllg;
 
@@ -100,14 +101,17 @@ bool slab_eligible(const sllg_level& L) { return L.nx * L.ny <= 1024 && L.nz >= 
 
 // Stream-plan tile shapes.  kind 0: k_stream<tx, ty, pz> (x-y window with a
 // recomputed ring); kind 1: k_rows<tx = threads, ty = cells per thread>
-// (full-width tiles, needs nx <= threads).
+// (full-width tiles, needs nx <= threads); kind 2: k_rows2<tx = threads,
+// ty = cells per thread> (full-width tiles, z-columns in registers).
 struct Shape {
     int kind, tx, ty, pz;
 };
 const Shape kShapes[] = {{0, 64, 8, 1},  {0, 32, 16, 1}, {0, 64, 16, 1}, {0, 32, 8, 2},
                          {0, 8, 24, 4},  {0, 8, 24, 2},  {0, 8, 24, 1},  {0, 16, 16, 2},
                          {0, 4, 12, 8},  {1, 192, 1, 1}, {1, 256, 1, 1}, {1, 256, 2, 1},
-                         {1, 512, 1, 1}, {1, 512, 2, 1}, {1, 1024, 1, 1}, {1, 256, 4, 1}};
+                         {1, 512, 1, 1}, {1, 512, 2, 1}, {1, 1024, 1, 1}, {1, 256, 4, 1},
+                         {2, 1024, 2, 1}, {2, 1024, 1, 1}, {2, 768, 2, 1}, {2, 512, 2, 1},
+                         {2, 256, 2, 1},  {2, 256, 1, 1},  {2, 192, 1, 1}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 const int kTzChoices[] = {1, 2, 4, 8, 16, 32, 64};
 
@@ -146,19 +150,37 @@ std::vector<std::pair<int, int>> row_windows(int ny, int R)
     return w;
 }
 
+// Predicted rows a full-width tile holds (kinds 1 and 2).
+int shape_rows(const sllg_level& L, const Shape& s)
+{
+    return s.kind == 1 ? (s.tx / L.nx) * s.ty : (s.tx * s.ty) / L.nx;
+}
+
+// Dynamic LDS of a k_rows2 tile: two m_n planes (predicted rows + 2) and
+// three m' planes (predicted rows), three components each.
+size_t rows2_lds(const sllg_level& L, const Shape& s)
+{
+    const int R = std::min(shape_rows(L, s), L.ny);
+    return sizeof(float) * (size_t)(6 * (R + 2) + 9 * R) * L.nx;
+}
+
 bool shape_fits(const sllg_level& L, const Shape& s)
 {
     if (s.kind == 0) return true;
     if (L.nx > s.tx) return false;
-    const int R = (s.tx / L.nx) * s.ty;
+    const int R = shape_rows(L, s);
+    if (s.kind == 2) {
+        if (R < L.ny && 2 * L.nx > s.tx) return false;   // the two extra rows need 2 nx threads
+        if (rows2_lds(L, s) > 160 * 1024 - 1024) return false;
+    }
     return !row_windows(L.ny, R).empty();
 }
 
 int64_t tiles_for(const sllg_level& L, const Shape& s, int tz)
 {
-    if (s.kind == 1) {
+    if (s.kind >= 1) {
         if (!shape_fits(L, s)) return 0;
-        return (int64_t)row_windows(L.ny, (s.tx / L.nx) * s.ty).size() * ceil_div(L.nz, tz);
+        return (int64_t)row_windows(L.ny, shape_rows(L, s)).size() * ceil_div(L.nz, tz);
     }
     return ceil_div(L.nx, s.tx) * ceil_div(L.ny, s.ty) * ceil_div(L.nz, tz);
 }
@@ -434,8 +456,8 @@ void build_tiles(sllg_ctx* C, LevelHost& h)
     for (int r = 0; r < h.ninst; ++r) {
         InstDev& I = C->h_insts[h.inst0 + r];
         I.tile0 = (int)C->h_tiles.size();
-        if (s.kind == 1) {
-            const auto rows = row_windows(h.in.ny, (s.tx / h.in.nx) * s.ty);
+        if (s.kind >= 1) {
+            const auto rows = row_windows(h.in.ny, shape_rows(h.in, s));
             for (int z0 = 0; z0 < h.in.nz; z0 += h.tz)
                 for (const auto& w : rows) {
                     TileDev t{};
@@ -757,9 +779,49 @@ hipError_t launch_rows_t(sllg_ctx* C, int level)
     return hipGetLastError();
 }
 
+template <int NT, int K>
+hipError_t launch_rows2_t(sllg_ctx* C, int level)
+{
+    const LevelHost& h = C->lv[level];
+    const size_t lds = rows2_lds(h.in, kShapes[h.shape]);
+    const bool axes = h.axes_off >= 0;
+    const void* fn = axes ? reinterpret_cast<const void*>(&k_rows2<NT, K, true>)
+                          : reinterpret_cast<const void*>(&k_rows2<NT, K, false>);
+    // raise the dynamic-LDS limit of the instantiation once per size
+    static size_t set_lds[2] = {0, 0};
+    if (lds > set_lds[axes]) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        set_lds[axes] = lds;
+    }
+    if (axes)
+        hipLaunchKernelGGL((k_rows2<NT, K, true>), dim3(h.ntiles), dim3(NT), lds, C->stream, C->d_tiles, C->d_insts,
+                           C->d_levels, C->d_buf0, C->d_buf1, C->d_axes, C->d_steps, h.tile0, (int)C->lay.max_tiles,
+                           C->d_partials, C->d_inst_cnt, C->d_launch_cnt + level, C->d_records, C->d_accs, C->d_ckpt,
+                           C->ckpt_every, C->d_status);
+    else
+        hipLaunchKernelGGL((k_rows2<NT, K, false>), dim3(h.ntiles), dim3(NT), lds, C->stream, C->d_tiles,
+                           C->d_insts, C->d_levels, C->d_buf0, C->d_buf1, C->d_axes, C->d_steps, h.tile0,
+                           (int)C->lay.max_tiles, C->d_partials, C->d_inst_cnt, C->d_launch_cnt + level, C->d_records,
+                           C->d_accs, C->d_ckpt, C->ckpt_every, C->d_status);
+    return hipGetLastError();
+}
+
 hipError_t dispatch_stream(sllg_ctx* C, int level)
 {
     const Shape s = kShapes[C->lv[level].shape];
+    if (s.kind == 2) {
+        switch (s.tx * 10 + s.ty) {
+        case 10242: return launch_rows2_t<1024, 2>(C, level);
+        case 10241: return launch_rows2_t<1024, 1>(C, level);
+        case 7682: return launch_rows2_t<768, 2>(C, level);
+        case 5122: return launch_rows2_t<512, 2>(C, level);
+        case 2562: return launch_rows2_t<256, 2>(C, level);
+        case 2561: return launch_rows2_t<256, 1>(C, level);
+        case 1921: return launch_rows2_t<192, 1>(C, level);
+        default: return hipErrorInvalidValue;
+        }
+    }
     if (s.kind == 1) {
         switch (s.tx * 10 + s.ty) {
         case 1921: return launch_rows_t<192, 1>(C, level);
@@ -1093,12 +1155,24 @@ int tune_stream(sllg_ctx* C, int level)
         double use;
         if (S.kind == 0) {
             use = (double)std::min(S.tx, h.in.nx) * std::min(S.ty, h.in.ny) / (S.tx * S.ty);
-        } else {
+        } else if (S.kind == 1) {
             const int TR = S.tx / h.in.nx;
             use = (double)(TR * h.in.nx) / S.tx * std::min(1.0, (double)h.in.ny / (TR * S.ty));
+        } else {
+            use = (double)std::min(shape_rows(h.in, S), h.in.ny) * h.in.nx / (S.tx * S.ty);
         }
         if (use < 0.5) continue;
-        for (int tz : kTzChoices) {
+        // powers of two, plus the depths whose tile count just fills k waves
+        // of one workgroup per CU
+        std::vector<int> tzs(std::begin(kTzChoices), std::end(kTzChoices));
+        const int64_t xy = tiles_for(h.in, S, h.in.nz) * h.ninst;   // tiles of one z chunk
+        for (int k = 1; k <= 4 && xy > 0; ++k) {
+            const int64_t chunks = (int64_t)k * C->num_cus / xy;
+            if (chunks < 1) continue;
+            const int tz = (int)ceil_div(h.in.nz, chunks);
+            if (std::find(tzs.begin(), tzs.end(), tz) == tzs.end()) tzs.push_back(tz);
+        }
+        for (int tz : tzs) {
             if (tz < S.pz || tz > h.in.nz * 2) continue;
             const int64_t nt = tiles_for(h.in, S, tz) * h.ninst;
             if (nt == 0) continue;
@@ -1751,6 +1825,31 @@ int sllg_set_slab_shape(sllg_ctx* C, int32_t level, int32_t kind, int32_t thread
         return fail(SLLG_E_INVAL, "slab kernel kind %d <%d,%d> with %d planes cannot hold level %d", kind, threads,
                     cells_per_thread, planes, level);
     }
+    return SLLG_OK;
+}
+
+int sllg_set_stream_shape(sllg_ctx* C, int32_t level, int32_t kind, int32_t a, int32_t b, int32_t c,
+                          int32_t planes)
+{
+    if (!C || level < 0 || level >= (int)C->lv.size()) return fail(SLLG_E_INVAL, "bad level");
+    LevelHost& h = C->lv[level];
+    int si = -1;
+    for (int i = 0; i < kNumShapes; ++i)
+        if (kShapes[i].kind == kind && kShapes[i].tx == a && kShapes[i].ty == b && kShapes[i].pz == c) si = i;
+    if (si < 0) return fail(SLLG_E_INVAL, "no stream kernel kind %d <%d,%d,%d>", kind, a, b, c);
+    if (planes < 1 || planes < kShapes[si].pz || !shape_fits(h.in, kShapes[si]) ||
+        tiles_for(h.in, kShapes[si], planes) * h.ninst > C->lay.max_tiles)
+        return fail(SLLG_E_INVAL, "stream kernel kind %d <%d,%d,%d> with %d planes cannot hold level %d", kind, a, b,
+                    c, planes, level);
+    h.plan = kPlanStream;
+    h.shape = si;
+    h.tz = planes;
+    h.forced = 1;
+    int rc = replan(C);
+    if (rc) return rc;
+    for (size_t l = 0; l < C->lv.size(); ++l)
+        HIP_OK(hipMemcpyAsync(C->d_steps + l, &C->lv[l].step, sizeof(int64_t), hipMemcpyHostToDevice, C->stream));
+    HIP_OK(hipStreamSynchronize(C->stream));
     return SLLG_OK;
 }
 

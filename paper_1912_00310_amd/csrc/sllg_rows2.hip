@@ -1,0 +1,245 @@
+// Streamed Heun step (one launch per step) with the vertical neighbours in
+// registers.
+//
+// A workgroup owns the rows [y0, y0 + nyt) of every x of one instance over
+// the planes [z0, z0 + nzt).  It predicts the window plus one ring row on
+// each side that lies inside the grid (rows [py0, py1)); the cells of that
+// region are dealt to the threads in row-major order, K per thread, and a
+// thread keeps its cells' whole z-columns: m_n of planes p-1, p, p+1 and the
+// plane p+2 in flight, the easy axes of p-1, p, p+1, and q and H_th of the
+// previous plane.  LDS holds only x-y planes: m_n of planes p and p - 1
+// (the predicted rows plus the rows py0 - 1 and py1, loaded by the first
+// 2*nx threads) and m' of planes p, p - 1 and p - 2; every buffer is written
+// once per plane and read by other threads only until the next barrier, so
+// one barrier per plane suffices, and a thread reads its own column's
+// earlier planes back from LDS instead of holding them.  At plane p the
+// workgroup
+//   1. writes m_n(p) to LDS and waits at the barrier,
+//   2. predicts plane p from LDS (x-y) and registers (z),
+//   3. writes m'(p) to the other LDS buffer,
+//   4. corrects plane p - 1 from m'(p - 1) in LDS (x-y) and registers (z),
+//      storing m_{n+1},
+//   5. shifts its registers and issues the loads of plane p + 3 (and the
+//      axes of plane p + 2).
+// The planes z0 - 1 and z0 + nzt are predicted for the window cells only
+// (their m' is needed only as a vertical neighbour).
+#include <hip/hip_runtime.h>
+
+#include "sllg_device.hpp"
+#include "sllg_types.hpp"
+
+namespace sllg {
+
+template <int NT, int K, bool AXES>
+__global__ __launch_bounds__(NT) void k_rows2(
+    const TileDev* __restrict__ tiles, const InstDev* __restrict__ insts,
+    const LevelDev* __restrict__ levels, float* __restrict__ buf0, float* __restrict__ buf1,
+    const float* __restrict__ axes, int64_t* __restrict__ steps, int tile_base, int ptiles,
+    double* __restrict__ partials, uint32_t* __restrict__ pend, uint32_t* __restrict__ launch_cnt,
+    double* __restrict__ records, AccDev* __restrict__ accs, float* __restrict__ ckpt, int ckpt_every,
+    int* __restrict__ status)
+{
+    extern __shared__ float lds[];
+    __shared__ double red[NT / 64];
+
+    const int tid = threadIdx.x;
+    const int tile = tile_base + static_cast<int>(blockIdx.x);
+    const TileDev T = tiles[tile];
+    const InstDev I = insts[T.inst];
+    const LevelDev& L = levels[I.level];
+    const int64_t n = steps[I.level];
+    const bool first_tile = tile == I.tile0;
+    if (first_tile && pend[T.inst]) {
+        fold_partials(I, L, n - 1, partials, ptiles, accs, T.inst, records, status);
+        if (tid == 0) pend[T.inst] = 0u;
+    }
+    if (n >= L.n_steps) return;
+
+    const float* __restrict__ mi = ((n & 1) ? buf1 : buf0) + I.state_off;
+    float* __restrict__ mo = ((n & 1) ? buf0 : buf1) + I.state_off;
+    const int nx = L.nx, ny = L.ny, nz = L.nz, N = L.ncell, nxy = nx * ny;
+    const int y0 = T.y0, yend = T.y0 + T.nyt;
+    const int z0 = T.z0, zend = T.z0 + T.nzt;
+    const int py0 = max(y0 - 1, 0), py1 = min(yend + 1, ny);
+    const int pz0 = max(z0 - 1, 0), pz1 = min(zend, nz - 1);
+    const int LC = (py1 - py0 + 2) * nx;   // LDS cells of an m_n plane (rows py0 - 1 .. py1)
+    const int PC = (py1 - py0) * nx;       // predicted cells
+    float* const Mn0 = lds;                // [2][3][LC]: m_n of planes p (buffer p & 1) and p - 1
+    float* const Mp0 = lds + 6 * LC;       // [3][3][PC]: m' of planes p, p - 1, p - 2 (buffer p % 3)
+    const float hz0 = static_cast<float>(L.hz_amp * wave_at(L, n));
+    const float hz1 = static_cast<float>(L.hz_amp * wave_at(L, n + 1));
+    const bool do_ckpt = (ckpt != nullptr) && ckpt_every > 0 && (n % ckpt_every) == 0;
+    float* cp = do_ckpt ? ckpt + I.ckpt_off + (n / ckpt_every) * 3 * static_cast<int64_t>(N) : nullptr;
+    const float* ax = axes + L.axes_off;
+    const V3 u0 = V3{L.ux, L.uy, L.uz};
+
+    // own cells: index ii in the predicted region (the m' plane index; the
+    // m_n LDS index is ii + nx, the plane index ii + py0 nx) and which x-y
+    // neighbours exist (bits: x-1, x+1, y-1, y+1); neighbours outside the
+    // grid are replaced by the cell itself
+    int ii[K], edge[K];
+    bool on[K], win[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const int i = tid + j * NT;
+        on[j] = i < PC;
+        ii[j] = on[j] ? i : 0;
+        const int y = py0 + ii[j] / nx, x = ii[j] - (y - py0) * nx;
+        win[j] = on[j] && y >= y0 && y < yend;
+        edge[j] = (x > 0 ? 1 : 0) | (x < nx - 1 ? 2 : 0) | (y > 0 ? 4 : 0) | (y < ny - 1 ? 8 : 0);
+    }
+    const int gofs = py0 * nx;   // plane index of predicted-region index 0
+    // the rows py0 - 1 and py1 (when inside the grid) are loaded by threads
+    // [0, nx) and [nx, 2 nx)
+    const bool ex_lo = tid < nx && py0 > 0;
+    const bool ex_hi = tid >= nx && tid < 2 * nx && py1 < ny;
+    const bool ex = ex_lo || ex_hi;
+    const int ex_x = ex_lo ? tid : tid - nx;
+    const int ex_gc = ex ? ex_x + nx * (ex_lo ? py0 - 1 : py1) : 0;
+    const int ex_li = ex_lo ? ex_x : (py1 - py0 + 1) * nx + ex_x;
+
+    auto ld = [&](int z, int c) -> V3 {
+        const float* pl = mi + static_cast<int64_t>(min(z, nz - 1)) * nxy;
+        return V3{pl[c], pl[N + c], pl[2 * N + c]};
+    };
+    auto ldu = [&](int z, int c) -> V3 {
+        const float* pl = ax + static_cast<int64_t>(min(z, nz - 1)) * nxy;
+        return V3{pl[c], pl[N + c], pl[2 * N + c]};
+    };
+
+    auto xm = [&](int i, int e) { return (e & 1) ? i - 1 : i; };
+    auto xp = [&](int i, int e) { return (e & 2) ? i + 1 : i; };
+    auto ym = [&](int i, int e) { return (e & 4) ? i - nx : i; };
+    auto yp = [&](int i, int e) { return (e & 8) ? i + nx : i; };
+
+    V3 B[K], Cn[K], Dn[K];                // m_n of planes p, p+1, p+2
+    V3 UA[K], UB[K], UC[K];               // axes of planes p-1, p, p+1
+    V3 qm1[K], hm1[K];                    // q, H_th of plane p-1
+    V3 EB{0, 0, 0}, EC{0, 0, 0}, ED{0, 0, 0};   // extra row: planes p, p+1, p+2
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        B[j] = Cn[j] = Dn[j] = UA[j] = UB[j] = UC[j] = V3{0, 0, 0};
+        qm1[j] = hm1[j] = V3{0, 0, 0};
+        if (!on[j]) continue;
+        if (pz0 > 0) {
+            // plane pz0 - 1 of the own column, the lower neighbour of the first plane
+            const V3 a = ld(pz0 - 1, ii[j] + gofs);
+            float* Ma = Mn0 + ((pz0 - 1) & 1) * 3 * LC;
+            Ma[ii[j] + nx] = a.x;
+            Ma[LC + ii[j] + nx] = a.y;
+            Ma[2 * LC + ii[j] + nx] = a.z;
+        }
+        B[j] = ld(pz0, (ii[j] + gofs));
+        Cn[j] = ld(pz0 + 1, (ii[j] + gofs));
+        Dn[j] = ld(pz0 + 2, (ii[j] + gofs));
+        if (AXES) {
+            UB[j] = ldu(pz0, (ii[j] + gofs));
+            UC[j] = ldu(pz0 + 1, (ii[j] + gofs));
+        }
+    }
+    if (ex) {
+        EB = ld(pz0, ex_gc);
+        EC = ld(pz0 + 1, ex_gc);
+        ED = ld(pz0 + 2, ex_gc);
+    }
+
+    float msum = 0.0f;
+    const int plast = zend == nz ? nz : pz1;   // the last plane holds only a corrector when zend = nz
+    int b3 = pz0 % 3;                          // p % 3
+    for (int p = pz0; p <= plast; ++p) {
+        const bool predict = p <= pz1;
+        const bool halo_plane = p < z0 || p >= zend;
+        const int b = p & 1;
+        float* Mn = Mn0 + b * 3 * LC;
+        const float* Mo = Mn0 + (b ^ 1) * 3 * LC;                       // m_n of plane p - 1
+        float* Mp = Mp0 + b3 * 3 * PC;
+        const float* Mq = Mp0 + (b3 == 0 ? 2 : b3 - 1) * 3 * PC;      // m' of plane p - 1
+        const float* Mr = Mp0 + (b3 == 2 ? 0 : b3 + 1) * 3 * PC;      // m' of plane p - 2
+        b3 = b3 == 2 ? 0 : b3 + 1;
+        // ---- 1. m_n(p) to LDS
+        if (predict) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                if (!on[j]) continue;
+                const int l = ii[j] + nx;
+                Mn[l] = B[j].x;
+                Mn[LC + l] = B[j].y;
+                Mn[2 * LC + l] = B[j].z;
+            }
+            if (ex) {
+                Mn[ex_li] = EB.x;
+                Mn[LC + ex_li] = EB.y;
+                Mn[2 * LC + ex_li] = EB.z;
+            }
+        }
+        lds_barrier();
+        // ---- 2. predictor at plane p; 3. m'(p) to LDS
+        V3 mpn[K], qn[K], hn[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            mpn[j] = qn[j] = hn[j] = V3{0, 0, 0};
+            if (!predict || !on[j] || (halo_plane && !win[j])) continue;
+            const V3 m = B[j];
+            auto at = [&](int i) { return v3(Mn[i], Mn[LC + i], Mn[2 * LC + i]); };
+            const int l = ii[j] + nx, e = edge[j];
+            const V3 exs = nb_sum(m, at(xm(l, e)), at(xp(l, e)), at(ym(l, e)), at(yp(l, e)),
+                                  p > 0 ? v3(Mo[l], Mo[LC + l], Mo[2 * LC + l]) : m, p < nz - 1 ? Cn[j] : m);
+            hn[j] = thermal_field(L, I.seed, static_cast<uint32_t>((ii[j] + gofs) + nxy * p), n);
+            heun_predict(L, m, exs, AXES ? UB[j] : u0, hz0, hn[j], mpn[j], qn[j]);
+            Mp[ii[j]] = mpn[j].x;
+            Mp[PC + ii[j]] = mpn[j].y;
+            Mp[2 * PC + ii[j]] = mpn[j].z;
+        }
+        // ---- 4. corrector at plane p - 1
+        const int cz = p - 1;
+        if (cz >= z0 && cz < zend) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                if (!win[j]) continue;
+                auto at = [&](int i) { return v3(Mq[i], Mq[PC + i], Mq[2 * PC + i]); };
+                const int i = ii[j], e = edge[j];
+                const V3 mpc = at(i);
+                const V3 exs = nb_sum(mpc, at(xm(i, e)), at(xp(i, e)), at(ym(i, e)), at(yp(i, e)),
+                                      cz > 0 ? v3(Mr[i], Mr[PC + i], Mr[2 * PC + i]) : mpc, predict ? mpn[j] : mpc);
+                const V3 mn1 = heun_correct(L, mpc, exs, AXES ? UA[j] : u0, hz1, hm1[j], qm1[j]);
+                float* o = mo + static_cast<int64_t>(cz) * nxy;
+                o[(ii[j] + gofs)] = mn1.x;
+                o[N + (ii[j] + gofs)] = mn1.y;
+                o[2 * N + (ii[j] + gofs)] = mn1.z;
+                msum += mn1.z;
+                if (do_ckpt) {
+                    float* q = cp + static_cast<int64_t>(cz) * nxy;
+                    const int l = ii[j] + nx;
+                    q[(ii[j] + gofs)] = Mo[l];
+                    q[N + (ii[j] + gofs)] = Mo[LC + l];
+                    q[2 * N + (ii[j] + gofs)] = Mo[2 * LC + l];
+                }
+            }
+        }
+        // ---- 5. shift the columns; loads of plane p + 3 and axes of p + 2
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            qm1[j] = qn[j];
+            hm1[j] = hn[j];
+            B[j] = Cn[j];
+            Cn[j] = Dn[j];
+            if (on[j] && p + 3 <= pz1 + 1) Dn[j] = ld(p + 3, (ii[j] + gofs));
+            if (AXES) {
+                UA[j] = UB[j];
+                UB[j] = UC[j];
+                if (on[j] && p + 2 <= pz1) UC[j] = ldu(p + 2, (ii[j] + gofs));
+            }
+        }
+        if (ex) {
+            EB = EC;
+            EC = ED;
+            if (p + 3 <= pz1) ED = ld(p + 3, ex_gc);
+        }
+    }
+
+    const double tot = block_sum<NT>(msum, red);
+    stream_block_end(tot, n, tile, ptiles, partials, first_tile, pend, T.inst, launch_cnt, steps, I.level,
+                     L.n_steps);
+}
+
+}  // namespace sllg

@@ -89,6 +89,8 @@ def lib():
             "sllg_set_state": (C.c_int, [vp, C.c_int32, C.c_int32, P(C.c_float)]),
             "sllg_set_plan": (C.c_int, [vp, C.c_int32, C.c_int32]),
             "sllg_set_slab_shape": (C.c_int, [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+            "sllg_set_stream_shape": (C.c_int, [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                                C.c_int32]),
             "sllg_philox_probe": (C.c_int, [C.c_uint64, C.c_uint32, C.c_uint32, P(C.c_uint32),
                                             P(C.c_uint64), C.c_int32, P(C.c_uint32), P(C.c_float), vp, vp]),
             "sllg_get_axes": (C.c_int, [vp, C.c_int32, P(C.c_float)]),
@@ -109,7 +111,7 @@ def exported_symbols():
         "sllg_workspace_bytes", "sllg_init", "sllg_run_sweep", "sllg_run_steps", "sllg_reset",
         "sllg_loop", "sllg_grad", "sllg_last_error", "sllg_free", "sllg_level_params",
         "sllg_level_step", "sllg_level_kernel", "sllg_get_state", "sllg_set_state", "sllg_set_plan",
-        "sllg_set_slab_shape",
+        "sllg_set_slab_shape", "sllg_set_stream_shape",
         "sllg_philox_probe", "sllg_get_axes", "sllg_set_timing", "sllg_kernel_time")]
 
 
@@ -259,6 +261,10 @@ class Sim:
         """Slab plan with a given kernel (kind 0: halo recompute, 1: m' exchange) and thickness."""
         _check("sllg_set_slab_shape", lib().sllg_set_slab_shape(self.ctx, level, kind, threads,
                                                                 cells_per_thread, planes))
+
+    def set_stream_shape(self, level: int, kind: int, a: int, b: int, c: int, planes: int):
+        """Streamed plan with a given tile kernel (kind 0: x-y window <a,b,c>, 1: rows <a,b>, 2: rows2 <a,b>)."""
+        _check("sllg_set_stream_shape", lib().sllg_set_stream_shape(self.ctx, level, kind, a, b, c, planes))
 
     def axes(self, level: int = 0) -> np.ndarray:
         out = np.zeros(3 * self.ncell(level), dtype=np.float32)

@@ -74,11 +74,13 @@ def test_axes_match_oracle(P, orc):
     sim.close()
 
 
-def _trajectory_check(P, orc, wl, nsteps, plan=None, every=1, tol=1e-5, check_loop=True):
+def _trajectory_check(P, orc, wl, nsteps, plan=None, every=1, tol=1e-5, check_loop=True, stream_shape=None):
     lv = oracle_level(wl)
     sim = P.Sim(wl["material"], wl["levels"])
     if plan is not None:
         sim.set_plan(0, plan)
+    if stream_shape is not None:
+        sim.set_stream_shape(0, *stream_shape)
     u = orc.make_axes(lv)
     N = lv["nx"] * lv["ny"] * lv["nz"]
     m_ref = np.tile([0.0, 0.0, 1.0], (N, 1))
@@ -247,3 +249,42 @@ def test_slab_plan_chunks_and_checkpoints(P, shape):
         sim.close()
     assert np.array_equal(res[P.PLAN_RESIDENT][0], res[P.PLAN_SLAB][0])
     assert np.allclose(res[P.PLAN_RESIDENT][1][0], res[P.PLAN_SLAB][1][0], rtol=1e-5)
+
+
+# ---- full-width streamed kernel with the z-columns in registers (kind 2)
+ROWS2 = [(2, 1024, 2, 1), (2, 1024, 1, 1), (2, 768, 2, 1), (2, 512, 2, 1), (2, 256, 2, 1), (2, 192, 1, 1)]
+
+
+@pytest.mark.parametrize("shape", ROWS2)
+@pytest.mark.parametrize("dims,tz", [((40, 36, 20), 7), ((13, 7, 5), 2), ((1, 1, 9), 4), ((70, 9, 3), 1),
+                                     ((96, 40, 6), 3)])
+def test_rows2_ragged_tiles_with_cone(P, orc, shape, dims, tz):
+    wl = W.workload("block_b2_cone10")
+    wl["levels"][0].update(nx=dims[0], ny=dims[1], nz=dims[2])
+    wl["material"]["sweep_Oe_per_ns"] = 1e5
+    probe = P.Sim(wl["material"], wl["levels"])
+    try:
+        probe.set_stream_shape(0, *shape, tz)
+    except P.SllgError:
+        probe.close()
+        pytest.skip("tiling does not fit this grid")
+    probe.close()
+    _trajectory_check(P, orc, wl, 60, every=20, stream_shape=(*shape, tz))
+
+
+@pytest.mark.parametrize("cone", [10.0, 0.0])
+def test_rows2_bit_identical_to_window_kernel(P, cone):
+    # a 128 x 128 x 24 slice of the block, 20 steps: every streamed kernel
+    # gives the same bits
+    wl = W.workload("block_b2_cone10")
+    wl["levels"][0].update(nz=24, cone_deg=cone)
+    out = []
+    for shape in [(0, 64, 8, 1, 8), (2, 1024, 2, 1, 8), (2, 512, 2, 1, 5), (2, 1024, 1, 1, 24)]:
+        sim = P.Sim(wl["material"], wl["levels"])
+        sim.set_stream_shape(0, *shape)
+        sim.run_steps(20)
+        out.append((sim.get_state(0, 0), sim.loop(0, 0)[1]))
+        sim.close()
+    for st, mh in out[1:]:
+        assert np.array_equal(st, out[0][0])
+        assert np.abs(mh - out[0][1]).max() < 1e-6
