@@ -94,8 +94,11 @@ def main():
     steps = a.steps if a.steps is not None else (2 if heavy else 5)
     warmup = a.warmup if a.warmup is not None else 1
 
+    t_split = {"forward": 0.0, "grad": 0.0}
+
     def one_step():
         # one sweep (or window) of every level and realization
+        t = time.perf_counter()
         if window == n_sweep:
             sim.reset()
             sim.run_sweep()
@@ -104,7 +107,11 @@ def main():
                 sim.reset()
             sim.run_steps(window)
         if adjoint:
-            sim.grad(0)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            sim.grad(0)          # synchronises
+            t_split["forward"] += t1 - t
+            t_split["grad"] += time.perf_counter() - t1
         for l in range(len(levels)):
             sim.loop(l, -1)
 
@@ -113,6 +120,7 @@ def main():
     for _ in range(warmup):
         one_step()
     torch.cuda.synchronize()
+    t_split["forward"] = t_split["grad"] = 0.0
     # HIP events on the library's stream around the dominant kernel's launch
     # units (graph replays of 128 streamed steps, slab launches, or resident
     # launches)
@@ -171,6 +179,14 @@ def main():
         rl["hbm_equiv_GBps"] = round(gbs, 1)
         rl["valu_TOPs"] = round(tops, 3)
 
+    extra = {}
+    if adjoint:
+        extra["adjoint"] = {"forward_s_per_sweep": t_split["forward"] / steps,
+                            "grad_s_per_sweep": t_split["grad"] / steps,
+                            "grad_over_forward": t_split["grad"] / max(t_split["forward"], 1e-12)}
+    if len(levels) > 1 or levels[0]["n_real"] > 8:
+        extra["batched_vs_plain"] = plain_leg(Sim, torch, wl, dt / (steps * window))
+
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(wl, a.cpu_seconds)
@@ -215,8 +231,33 @@ def main():
         "loop": {str(l): {k: (None if isinstance(v, float) and math.isnan(v) else v)
                           for k, v in stats[l].items()} for l in stats},
     }
+    out.update(extra)
     print(json.dumps(out))
     sim.close()
+
+
+def plain_leg(Sim, torch, wl, batched_s_per_step, nsteps=2000):
+    """The same instances stepped one realization at a time: a context per
+    level holding a single realization (its own plan, tuned alike), timed
+    over nsteps and scaled by the number of realizations.  Both forms run the
+    same per-cell arithmetic, so their states are bit-identical."""
+    per_level = []
+    plain = 0.0
+    for lvd in wl["levels"]:
+        one = dict(lvd, n_real=1)
+        sim = Sim(wl["material"], [one])
+        sim.run_steps(64)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sim.run_steps(nsteps)
+        torch.cuda.synchronize()
+        s = (time.perf_counter() - t) / nsteps
+        per_level.append({"grid": f"{lvd['nx']}x{lvd['ny']}x{lvd['nz']}", "us_per_step_one_realization": s * 1e6,
+                          "kernel": sim.kernel_name(0)})
+        plain += s * lvd["n_real"]
+        sim.close()
+    return {"plain_us_per_step": plain * 1e6, "batched_us_per_step": batched_s_per_step * 1e6,
+            "speedup": plain / batched_s_per_step, "per_level": per_level}
 
 
 def source_digest():

@@ -1686,7 +1686,7 @@ int sllg_level_kernel(const sllg_ctx* C, int32_t level, char* name, int32_t cap)
         if (sh.kind == 0)
             snprintf(buf, sizeof(buf), "k_stream<%d,%d,%d> tz %d", sh.tx, sh.ty, sh.pz, h.tz);
         else
-            snprintf(buf, sizeof(buf), "k_rows<%d,%d>", sh.tx, sh.ty);
+            snprintf(buf, sizeof(buf), "%s<%d,%d> tz %d", sh.kind == 1 ? "k_rows" : "k_rows2", sh.tx, sh.ty, h.tz);
     } else if (h.plan == kPlanSlab) {
         const SlabKernel& k = kSlabKernels[h.slab_kernel];
         snprintf(buf, sizeof(buf), "%s<%d,%d> tz %d steps/launch %d", k.kind == 0 ? "k_slab" : "k_slab2", k.nt, k.k,
