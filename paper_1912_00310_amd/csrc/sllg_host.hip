@@ -911,6 +911,19 @@ hipError_t launch_slab_t(sllg_ctx* C, int level, int64_t n0, int ns, bool check_
         if (e != hipSuccess) return e;
     }
     uint32_t tag_base = seq << 11;
+    if (KIND == 0) {
+        // 32-bit words, tag bit ((n + 1) >> 1) & 1 in buffer (n + 1) & 1: fill
+        // the buffer of each of the launch's first two steps with the other bit
+        const size_t half = (size_t)h.nslab * 4 * 3 * h.in.nx * h.in.ny;
+        for (int k = 1; k <= 2; ++k) {
+            const int64_t m = n0 + k;
+            const int par = (int)(m & 1);
+            const uint32_t other = (uint32_t)(1 - ((m >> 1) & 1)) << 30;
+            e = hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(reinterpret_cast<uint32_t*>(xch) + par * half),
+                                  (int)other, half, C->stream);
+            if (e != hipSuccess) return e;
+        }
+    }
     double* part = C->d_spart + (int64_t)h.slab0 * kSlabChunk;
     int pstride = kSlabChunk;
     float* ckpt = C->d_ckpt;

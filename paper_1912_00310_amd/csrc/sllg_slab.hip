@@ -7,13 +7,16 @@
 //   1. predicts planes z0-1 .. z0+nzs (its own planes plus one halo plane on
 //      each side) from m_n in LDS, which holds planes z0-2 .. z0+nzs+1;
 //   2. corrects its own planes from m' in LDS and writes m_{n+1} over m_n;
-//   3. publishes its first two and last two planes of m_{n+1} into a
-//      step-parity exchange buffer as 64-bit words (value, tag), each written
-//      by one agent-coherent store, the tag naming the launch and the step;
+//   3. publishes its first two and last two planes of m_{n+1} (each plane
+//      once) into a step-parity exchange buffer, one 32-bit word per
+//      component written by one agent-coherent store: a component of a unit
+//      vector has |v| < 2, so bit 30 of its FP32 pattern is 0 and carries a
+//      tag bit that alternates between successive uses of a buffer;
 //   4. polls the words its z neighbours publish for the same step until every
 //      tag matches, and puts their values into its LDS halo.
-// A word carries its own step tag, so no separate flag or store
-// acknowledgement is needed: one trip through device memory per step.
+// A word carries its own tag, so no separate flag or store acknowledgement is
+// needed: one trip through device memory per step.  The host fills both
+// buffers with the opposite tags before each launch.
 // Neighbouring workgroups never drift apart by more than one step, so the
 // double-buffered exchange has no write-after-read hazard.  The per-step
 // partial sums of m_z go to a [slab][step] buffer that a fold kernel turns
@@ -36,6 +39,25 @@ struct SlabDev {
 };
 
 constexpr uint32_t kSlabSpinLimit = 1u << 20;
+constexpr uint32_t kTagBit = 1u << 30;
+
+// 32-bit exchange word: the FP32 pattern of |v| < 2 with bit 30 as the tag;
+// any other value (only after a numerical blow-up, which the loop fold
+// reports) is sent as +-1.5
+__device__ __forceinline__ void st_word32(uint32_t* p, float v, uint32_t tbit)
+{
+    const float s = fabsf(v) < 2.0f ? v : copysignf(1.5f, v);
+    __hip_atomic_store(p, __float_as_uint(s) | (tbit << 30), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_word32(const uint32_t* p)
+{
+    return __hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float word32_val(uint32_t w) { return __uint_as_float(w & ~kTagBit); }
+
+// exchange slot of own plane e (1-based) of a slab of nzs planes: the first
+// two planes use slots 0, 1, the last two slots 2, 3 unless already sent
+__device__ __forceinline__ int slab_slot(int e, int nzs) { return e <= 2 ? e - 1 : 2 + (e - (nzs - 1)); }
 constexpr int kSlabChunk = 1024;   // steps per launch (depth of the partials buffer)
 
 __device__ __forceinline__ void st_word(uint64_t* p, float v, uint32_t tag)
@@ -56,7 +78,7 @@ template <int NT, int K>
 __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, const InstDev* __restrict__ insts,
                                              const LevelDev* __restrict__ levels, float* __restrict__ buf0,
                                              float* __restrict__ buf1, const float* __restrict__ axes,
-                                             uint64_t* __restrict__ xch, uint32_t tag_base,
+                                             uint64_t* __restrict__ xch64, uint32_t tag_base,
                                              double* __restrict__ partials, int pstride, float* __restrict__ ckpt,
                                              int ckpt_every, int64_t n0, int nsteps, int* __restrict__ status)
 {
@@ -83,9 +105,12 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
     const int ixm = x > 0 ? c - 1 : c, ixp = x < nx - 1 ? c + 1 : c;
     const int iym = y > 0 ? c - nx : c, iyp = y < ny - 1 ? c + nx : c;
     // exchange slot (3 x P words) of one plane of one slab at a step parity
+    (void)tag_base;
+    uint32_t* const xch = reinterpret_cast<uint32_t*>(xch64);
     auto xslot = [&](int par, int slab, int slot) {
         return xch + ((static_cast<int64_t>(par) * gridDim.x + slab) * 4 + slot) * 3 * P;
     };
+    const int nzs_prev = S.prev >= 0 ? slabs[S.prev].nzs : 0;
     if (tid == 0) s_abort = 0;
 
     // ---- load m_n of planes z0-2 .. z0+nzs+1 (those inside the grid)
@@ -161,7 +186,7 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
         //         the boundary planes go out as tagged words
         float msum = 0.0f;
         const int par = static_cast<int>((n + 1) & 1);
-        const uint32_t tag = tag_base + static_cast<uint32_t>(st) + 1u;
+        const uint32_t tbit = static_cast<uint32_t>((n + 1) >> 1) & 1u;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int e = r + j * NPP;
@@ -183,18 +208,12 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
             mn(me, 1) = mnew.y;
             mn(me, 2) = mnew.z;
             msum += mnew.z;
-            // slots 0, 1 = first two planes, 2, 3 = last two
-            if (e <= 2) {
-                uint64_t* d = xslot(par, sid, e - 1);
-                st_word(d + c, mnew.x, tag);
-                st_word(d + P + c, mnew.y, tag);
-                st_word(d + 2 * P + c, mnew.z, tag);
-            }
-            if (e >= nzs - 1) {
-                uint64_t* d = xslot(par, sid, 2 + (e - (nzs - 1)));
-                st_word(d + c, mnew.x, tag);
-                st_word(d + P + c, mnew.y, tag);
-                st_word(d + 2 * P + c, mnew.z, tag);
+            // the first two and the last two planes, each once
+            if (e <= 2 || e >= nzs - 1) {
+                uint32_t* d = xslot(par, sid, slab_slot(e, nzs));
+                st_word32(d + c, mnew.x, tbit);
+                st_word32(d + P + c, mnew.y, tbit);
+                st_word32(d + 2 * P + c, mnew.z, tbit);
             }
         }
         {
@@ -208,15 +227,19 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
             const int me = h < 2 ? h : nzs + h;   // 0, 1, nzs+2, nzs+3
             const int z = z0 - 2 + me;
             if (z < 0 || z >= nz) continue;
-            const uint64_t* s = h < 2 ? xslot(par, S.prev, 2 + h) : xslot(par, S.next, h - 2);
-            uint64_t w0, w1, w2;
+            // below: the last two planes of the previous slab; above: the
+            // first two of the next
+            const uint32_t* s = h < 2 ? xslot(par, S.prev, slab_slot(nzs_prev - 1 + h, nzs_prev))
+                                      : xslot(par, S.next, h - 2);
+            uint32_t w0, w1, w2;
             uint32_t spins = 0;
             bool ok = true;
+            const uint32_t want = tbit << 30;
             for (;;) {
-                w0 = ld_word(s + c);
-                w1 = ld_word(s + P + c);
-                w2 = ld_word(s + 2 * P + c);
-                if (word_tag(w0) == tag && word_tag(w1) == tag && word_tag(w2) == tag) break;
+                w0 = ld_word32(s + c);
+                w1 = ld_word32(s + P + c);
+                w2 = ld_word32(s + 2 * P + c);
+                if ((w0 & kTagBit) == want && (w1 & kTagBit) == want && (w2 & kTagBit) == want) break;
                 if (++spins > kSlabSpinLimit) {
                     ok = false;
                     break;
@@ -228,9 +251,9 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
                 atomicOr(status, 2);
                 break;
             }
-            mn(me, 0) = word_val(w0);
-            mn(me, 1) = word_val(w1);
-            mn(me, 2) = word_val(w2);
+            mn(me, 0) = word32_val(w0);
+            mn(me, 1) = word32_val(w1);
+            mn(me, 2) = word32_val(w2);
         }
         __syncthreads();
         if (s_abort) return;
