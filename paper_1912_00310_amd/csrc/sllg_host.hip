@@ -991,9 +991,11 @@ hipError_t flush_level(sllg_ctx* C, int level)
 }
 
 // Graph of kGraphSteps consecutive stream launches of one level.
-int stream_graph(sllg_ctx* C, int level, hipGraphExec_t* out)
+// A HIP graph of nl streamed launches of a level (cached per level and nl).
+int stream_graph(sllg_ctx* C, int level, int nl, hipGraphExec_t* out)
 {
-    auto it = C->graphs.find(level);
+    const int key = level * 1024 + nl;
+    auto it = C->graphs.find(key);
     if (it != C->graphs.end()) {
         *out = it->second;
         return SLLG_OK;
@@ -1003,7 +1005,7 @@ int stream_graph(sllg_ctx* C, int level, hipGraphExec_t* out)
     C->stream = C->cap_stream;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(C->cap_stream, hipStreamCaptureModeThreadLocal);
-    for (int i = 0; i < kGraphSteps && e == hipSuccess; ++i) e = dispatch_stream(C, level);
+    for (int i = 0; i < nl && e == hipSuccess; ++i) e = dispatch_stream(C, level);
     hipError_t e2 = hipStreamEndCapture(C->cap_stream, &g);
     C->stream = user;
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -1014,7 +1016,7 @@ int stream_graph(sllg_ctx* C, int level, hipGraphExec_t* out)
     e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(SLLG_E_HIP, "graph instantiate: %s", hipGetErrorString(e));
-    C->graphs[level] = x;
+    C->graphs[key] = x;
     *out = x;
     return SLLG_OK;
 }
@@ -1032,8 +1034,12 @@ int run_steps(sllg_ctx* C, int64_t nsteps)
         while (k > 0) {
             // one launch unit: a graph of kGraphSteps launches or one launch;
             // every C->timing-th unit is bracketed by events
-            const bool graph = C->use_graph && k >= kGraphSteps;
-            const int64_t nl = graph ? kGraphSteps : 1;
+            // graphs of 128, 64, .., 8 launches; single launches below 8
+            int64_t nl = 1;
+            if (C->use_graph)
+                for (int g = kGraphSteps; g >= 8 && nl == 1; g /= 2)
+                    if (k >= g) nl = g;
+            const bool graph = nl > 1;
             const bool timed = C->timing > 0 && (C->unit_counter++ % C->timing) == 0;
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (timed) {
@@ -1044,7 +1050,7 @@ int run_steps(sllg_ctx* C, int64_t nsteps)
             }
             if (graph) {
                 hipGraphExec_t g = nullptr;
-                int rc = stream_graph(C, l, &g);
+                int rc = stream_graph(C, l, (int)nl, &g);
                 if (rc) return rc;
                 HIP_OK(hipGraphLaunch(g, C->stream));
             } else {
@@ -1615,13 +1621,15 @@ int sllg_loop(sllg_ctx* C, int32_t level, int32_t real, double* H_Oe, double* mH
     const int64_t npts = h.step / h.in.record_every + 1;
     if (n_out) *n_out = npts;
     if ((H_Oe || mH) && cap < npts) return fail(SLLG_E_CAPACITY, "need %lld entries", (long long)npts);
+    if (!H_Oe && !mH && !stats) return SLLG_OK;
     const int r0 = real < 0 ? 0 : real, r1 = real < 0 ? h.ninst : real + 1;
-    std::vector<double> rec((size_t)(r1 - r0) * h.n_rec);
+    // only the points recorded so far
+    std::vector<double> rec((size_t)(r1 - r0) * npts);
     std::vector<AccDev> acc(r1 - r0);
     for (int r = r0; r < r1; ++r) {
         const InstDev& I = C->h_insts[h.inst0 + r];
-        HIP_OK(hipMemcpyAsync(rec.data() + (size_t)(r - r0) * h.n_rec, C->d_records + I.rec_off,
-                              sizeof(double) * h.n_rec, hipMemcpyDeviceToHost, C->stream));
+        HIP_OK(hipMemcpyAsync(rec.data() + (size_t)(r - r0) * npts, C->d_records + I.rec_off,
+                              sizeof(double) * npts, hipMemcpyDeviceToHost, C->stream));
     }
     HIP_OK(hipMemcpyAsync(acc.data(), C->d_accs + h.inst0 + r0, sizeof(AccDev) * (r1 - r0),
                           hipMemcpyDeviceToHost, C->stream));
@@ -1630,7 +1638,7 @@ int sllg_loop(sllg_ctx* C, int32_t level, int32_t real, double* H_Oe, double* mH
     const double hz_oe = h.hz_amp / kOe;
     for (int64_t k = 0; k < npts; ++k) H[k] = hz_oe * wave_host(h, C->mat.wave, k * h.in.record_every);
     for (int r = 0; r < r1 - r0; ++r)
-        for (int64_t k = 0; k < npts; ++k) m[k] += rec[(size_t)r * h.n_rec + k];
+        for (int64_t k = 0; k < npts; ++k) m[k] += rec[(size_t)r * npts + k];
     for (int64_t k = 0; k < npts; ++k) m[k] /= (double)(r1 - r0);
     if (H_Oe) std::memcpy(H_Oe, H.data(), sizeof(double) * npts);
     if (mH) std::memcpy(mH, m.data(), sizeof(double) * npts);
