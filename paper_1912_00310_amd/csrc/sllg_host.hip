@@ -157,11 +157,11 @@ int shape_rows(const sllg_level& L, const Shape& s)
 }
 
 // Dynamic LDS of a k_rows2 tile: two m_n planes (predicted rows + 2) and
-// three m' planes (predicted rows), three components each.
+// two m' planes (predicted rows), one float4 per cell.
 size_t rows2_lds(const sllg_level& L, const Shape& s)
 {
     const int R = std::min(shape_rows(L, s), L.ny);
-    return sizeof(float) * (size_t)(6 * (R + 2) + 9 * R) * L.nx;
+    return 16 * (size_t)(2 * (R + 2) + 2 * R) * L.nx;
 }
 
 bool shape_fits(const sllg_level& L, const Shape& s)

@@ -6,13 +6,14 @@
 // each side that lies inside the grid (rows [py0, py1)); the cells of that
 // region are dealt to the threads in row-major order, K per thread, and a
 // thread keeps its cells' whole z-columns: m_n of planes p-1, p, p+1 and the
-// plane p+2 in flight, the easy axes of p-1, p, p+1, and q and H_th of the
-// previous plane.  LDS holds only x-y planes: m_n of planes p and p - 1
-// (the predicted rows plus the rows py0 - 1 and py1, loaded by the first
-// 2*nx threads) and m' of planes p, p - 1 and p - 2; every buffer is written
-// once per plane and read by other threads only until the next barrier, so
-// one barrier per plane suffices, and a thread reads its own column's
-// earlier planes back from LDS instead of holding them.  At plane p the
+// plane p+2 in flight, the easy axes of p-1, p, p+1, q and H_th of the
+// previous plane and m' of the plane before.  LDS holds only x-y planes, one
+// float4 per cell: m_n of planes p and p - 1 (the predicted rows plus the rows
+// py0 - 1 and py1, loaded by the first 2*nx threads) and m' of planes p and
+// p - 1; every buffer is written once per plane and read by other threads
+// only until the next barrier, so one barrier per plane suffices, and a
+// thread reads its own column's previous plane back from LDS.  Global
+// accesses are buffer instructions with 32-bit offsets.  At plane p the
 // workgroup
 //   1. writes m_n(p) to LDS and waits at the barrier,
 //   2. predicts plane p from LDS (x-y) and registers (z),
@@ -30,6 +31,9 @@
 
 namespace sllg {
 
+// third descriptor word of a raw (unformatted) buffer resource on gfx9
+constexpr int kBufDword3 = 0x00020000;
+
 template <int NT, int K, bool AXES>
 __global__ __launch_bounds__(NT) void k_rows2(
     const TileDev* __restrict__ tiles, const InstDev* __restrict__ insts,
@@ -39,7 +43,7 @@ __global__ __launch_bounds__(NT) void k_rows2(
     double* __restrict__ records, AccDev* __restrict__ accs, float* __restrict__ ckpt, int ckpt_every,
     int* __restrict__ status)
 {
-    extern __shared__ float lds[];
+    extern __shared__ float4 lds_rows2[];
     __shared__ double red[NT / 64];
 
     const int tid = threadIdx.x;
@@ -64,8 +68,9 @@ __global__ __launch_bounds__(NT) void k_rows2(
     const int pz0 = max(z0 - 1, 0), pz1 = min(zend, nz - 1);
     const int LC = (py1 - py0 + 2) * nx;   // LDS cells of an m_n plane (rows py0 - 1 .. py1)
     const int PC = (py1 - py0) * nx;       // predicted cells
-    float* const Mn0 = lds;                // [2][3][LC]: m_n of planes p (buffer p & 1) and p - 1
-    float* const Mp0 = lds + 6 * LC;       // [3][3][PC]: m' of planes p, p - 1, p - 2 (buffer p % 3)
+    // cells as float4 (x, y, z, unused): one 16-byte LDS access per neighbour
+    float4* const Mn0 = lds_rows2;            // [2][LC]: m_n of planes p (buffer p & 1) and p - 1
+    float4* const Mp0 = lds_rows2 + 2 * LC;   // [2][PC]: m' of planes p (buffer p & 1) and p - 1
     const float hz0 = static_cast<float>(L.hz_amp * wave_at(L, n));
     const float hz1 = static_cast<float>(L.hz_amp * wave_at(L, n + 1));
     const bool do_ckpt = (ckpt != nullptr) && ckpt_every > 0 && (n % ckpt_every) == 0;
@@ -98,14 +103,39 @@ __global__ __launch_bounds__(NT) void k_rows2(
     const int ex_gc = ex ? ex_x + nx * (ex_lo ? py0 - 1 : py1) : 0;
     const int ex_li = ex_lo ? ex_x : (py1 - py0 + 1) * nx + ex_x;
 
-    auto ld = [&](int z, int c) -> V3 {
-        const float* pl = mi + static_cast<int64_t>(min(z, nz - 1)) * nxy;
-        return V3{pl[c], pl[N + c], pl[2 * N + c]};
+    // global accesses as buffer instructions over one instance's planes: a
+    // 32-bit lane byte offset plus a wave-uniform plane byte offset, so no
+    // per-lane 64-bit address arithmetic (out-of-range offsets read 0)
+    const uint32_t region = 12u * static_cast<uint32_t>(N);   // bytes of mx | my | mz
+    const __amdgpu_buffer_rsrc_t r_in = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(mi), 0, region, kBufDword3);
+    const __amdgpu_buffer_rsrc_t r_out = __builtin_amdgcn_make_buffer_rsrc(mo, 0, region, kBufDword3);
+    const __amdgpu_buffer_rsrc_t r_ax = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(ax), 0, region, kBufDword3);
+    const __amdgpu_buffer_rsrc_t r_ck = __builtin_amdgcn_make_buffer_rsrc(do_ckpt ? cp : mo, 0, region, kBufDword3);
+    auto plane_ofs = [&](int z) { return static_cast<uint32_t>(min(z, nz - 1)) * static_cast<uint32_t>(nxy) * 4u; };
+    auto ld = [&](int z, uint32_t off) -> V3 {
+        const uint32_t pz = plane_ofs(z);
+        return V3{__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r_in, off, pz, 0)),
+                  __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r_in, off, pz + 4u * N, 0)),
+                  __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r_in, off, pz + 8u * N, 0))};
     };
-    auto ldu = [&](int z, int c) -> V3 {
-        const float* pl = ax + static_cast<int64_t>(min(z, nz - 1)) * nxy;
-        return V3{pl[c], pl[N + c], pl[2 * N + c]};
+    auto ldu = [&](int z, uint32_t off) -> V3 {
+        const uint32_t pz = plane_ofs(z);
+        return V3{__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r_ax, off, pz, 0)),
+                  __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r_ax, off, pz + 4u * N, 0)),
+                  __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r_ax, off, pz + 8u * N, 0))};
     };
+    auto st3 = [&](__amdgpu_buffer_rsrc_t r, int z, uint32_t off, V3 v) {
+        const uint32_t pz = plane_ofs(z);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v.x), r, off, pz, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v.y), r, off, pz + 4u * N, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v.z), r, off, pz + 8u * N, 0);
+    };
+    uint32_t gb[K];   // byte offset of each own cell within a plane
+#pragma unroll
+    for (int j = 0; j < K; ++j) gb[j] = static_cast<uint32_t>(ii[j] + gofs) * 4u;
+    const uint32_t ex_gb = static_cast<uint32_t>(ex_gc) * 4u;
+    auto f4 = [](V3 v) { return make_float4(v.x, v.y, v.z, 0.0f); };
+    auto v34 = [](float4 v) { return V3{v.x, v.y, v.z}; };
 
     auto xm = [&](int i, int e) { return (e & 1) ? i - 1 : i; };
     auto xp = [&](int i, int e) { return (e & 2) ? i + 1 : i; };
@@ -115,62 +145,49 @@ __global__ __launch_bounds__(NT) void k_rows2(
     V3 B[K], Cn[K], Dn[K];                // m_n of planes p, p+1, p+2
     V3 UA[K], UB[K], UC[K];               // axes of planes p-1, p, p+1
     V3 qm1[K], hm1[K];                    // q, H_th of plane p-1
+    V3 mpm2[K];                           // m' of plane p-2 (own cells)
     V3 EB{0, 0, 0}, EC{0, 0, 0}, ED{0, 0, 0};   // extra row: planes p, p+1, p+2
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         B[j] = Cn[j] = Dn[j] = UA[j] = UB[j] = UC[j] = V3{0, 0, 0};
-        qm1[j] = hm1[j] = V3{0, 0, 0};
+        qm1[j] = hm1[j] = mpm2[j] = V3{0, 0, 0};
         if (!on[j]) continue;
         if (pz0 > 0) {
             // plane pz0 - 1 of the own column, the lower neighbour of the first plane
-            const V3 a = ld(pz0 - 1, ii[j] + gofs);
-            float* Ma = Mn0 + ((pz0 - 1) & 1) * 3 * LC;
-            Ma[ii[j] + nx] = a.x;
-            Ma[LC + ii[j] + nx] = a.y;
-            Ma[2 * LC + ii[j] + nx] = a.z;
+            Mn0[((pz0 - 1) & 1) * LC + ii[j] + nx] = f4(ld(pz0 - 1, gb[j]));
         }
-        B[j] = ld(pz0, (ii[j] + gofs));
-        Cn[j] = ld(pz0 + 1, (ii[j] + gofs));
-        Dn[j] = ld(pz0 + 2, (ii[j] + gofs));
+        B[j] = ld(pz0, gb[j]);
+        Cn[j] = ld(pz0 + 1, gb[j]);
+        Dn[j] = ld(pz0 + 2, gb[j]);
         if (AXES) {
-            UB[j] = ldu(pz0, (ii[j] + gofs));
-            UC[j] = ldu(pz0 + 1, (ii[j] + gofs));
+            UB[j] = ldu(pz0, gb[j]);
+            UC[j] = ldu(pz0 + 1, gb[j]);
         }
     }
     if (ex) {
-        EB = ld(pz0, ex_gc);
-        EC = ld(pz0 + 1, ex_gc);
-        ED = ld(pz0 + 2, ex_gc);
+        EB = ld(pz0, ex_gb);
+        EC = ld(pz0 + 1, ex_gb);
+        ED = ld(pz0 + 2, ex_gb);
     }
 
     float msum = 0.0f;
     const int plast = zend == nz ? nz : pz1;   // the last plane holds only a corrector when zend = nz
-    int b3 = pz0 % 3;                          // p % 3
     for (int p = pz0; p <= plast; ++p) {
         const bool predict = p <= pz1;
         const bool halo_plane = p < z0 || p >= zend;
         const int b = p & 1;
-        float* Mn = Mn0 + b * 3 * LC;
-        const float* Mo = Mn0 + (b ^ 1) * 3 * LC;                       // m_n of plane p - 1
-        float* Mp = Mp0 + b3 * 3 * PC;
-        const float* Mq = Mp0 + (b3 == 0 ? 2 : b3 - 1) * 3 * PC;      // m' of plane p - 1
-        const float* Mr = Mp0 + (b3 == 2 ? 0 : b3 + 1) * 3 * PC;      // m' of plane p - 2
-        b3 = b3 == 2 ? 0 : b3 + 1;
+        float4* Mn = Mn0 + b * LC;
+        const float4* Mo = Mn0 + (b ^ 1) * LC;                      // m_n of plane p - 1
+        float4* Mp = Mp0 + b * PC;
+        const float4* Mq = Mp0 + (b ^ 1) * PC;                      // m' of plane p - 1
         // ---- 1. m_n(p) to LDS
         if (predict) {
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 if (!on[j]) continue;
-                const int l = ii[j] + nx;
-                Mn[l] = B[j].x;
-                Mn[LC + l] = B[j].y;
-                Mn[2 * LC + l] = B[j].z;
+                Mn[ii[j] + nx] = f4(B[j]);
             }
-            if (ex) {
-                Mn[ex_li] = EB.x;
-                Mn[LC + ex_li] = EB.y;
-                Mn[2 * LC + ex_li] = EB.z;
-            }
+            if (ex) Mn[ex_li] = f4(EB);
         }
         lds_barrier();
         // ---- 2. predictor at plane p; 3. m'(p) to LDS
@@ -180,15 +197,12 @@ __global__ __launch_bounds__(NT) void k_rows2(
             mpn[j] = qn[j] = hn[j] = V3{0, 0, 0};
             if (!predict || !on[j] || (halo_plane && !win[j])) continue;
             const V3 m = B[j];
-            auto at = [&](int i) { return v3(Mn[i], Mn[LC + i], Mn[2 * LC + i]); };
             const int l = ii[j] + nx, e = edge[j];
-            const V3 exs = nb_sum(m, at(xm(l, e)), at(xp(l, e)), at(ym(l, e)), at(yp(l, e)),
-                                  p > 0 ? v3(Mo[l], Mo[LC + l], Mo[2 * LC + l]) : m, p < nz - 1 ? Cn[j] : m);
+            const V3 exs = nb_sum(m, v34(Mn[xm(l, e)]), v34(Mn[xp(l, e)]), v34(Mn[ym(l, e)]), v34(Mn[yp(l, e)]),
+                                  p > 0 ? v34(Mo[l]) : m, p < nz - 1 ? Cn[j] : m);
             hn[j] = thermal_field(L, I.seed, static_cast<uint32_t>((ii[j] + gofs) + nxy * p), n);
             heun_predict(L, m, exs, AXES ? UB[j] : u0, hz0, hn[j], mpn[j], qn[j]);
-            Mp[ii[j]] = mpn[j].x;
-            Mp[PC + ii[j]] = mpn[j].y;
-            Mp[2 * PC + ii[j]] = mpn[j].z;
+            Mp[ii[j]] = f4(mpn[j]);
         }
         // ---- 4. corrector at plane p - 1
         const int cz = p - 1;
@@ -196,24 +210,14 @@ __global__ __launch_bounds__(NT) void k_rows2(
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 if (!win[j]) continue;
-                auto at = [&](int i) { return v3(Mq[i], Mq[PC + i], Mq[2 * PC + i]); };
                 const int i = ii[j], e = edge[j];
-                const V3 mpc = at(i);
-                const V3 exs = nb_sum(mpc, at(xm(i, e)), at(xp(i, e)), at(ym(i, e)), at(yp(i, e)),
-                                      cz > 0 ? v3(Mr[i], Mr[PC + i], Mr[2 * PC + i]) : mpc, predict ? mpn[j] : mpc);
+                const V3 mpc = v34(Mq[i]);
+                const V3 exs = nb_sum(mpc, v34(Mq[xm(i, e)]), v34(Mq[xp(i, e)]), v34(Mq[ym(i, e)]), v34(Mq[yp(i, e)]),
+                                      cz > 0 ? mpm2[j] : mpc, predict ? mpn[j] : mpc);
                 const V3 mn1 = heun_correct(L, mpc, exs, AXES ? UA[j] : u0, hz1, hm1[j], qm1[j]);
-                float* o = mo + static_cast<int64_t>(cz) * nxy;
-                o[(ii[j] + gofs)] = mn1.x;
-                o[N + (ii[j] + gofs)] = mn1.y;
-                o[2 * N + (ii[j] + gofs)] = mn1.z;
+                st3(r_out, cz, gb[j], mn1);
                 msum += mn1.z;
-                if (do_ckpt) {
-                    float* q = cp + static_cast<int64_t>(cz) * nxy;
-                    const int l = ii[j] + nx;
-                    q[(ii[j] + gofs)] = Mo[l];
-                    q[N + (ii[j] + gofs)] = Mo[LC + l];
-                    q[2 * N + (ii[j] + gofs)] = Mo[2 * LC + l];
-                }
+                if (do_ckpt) st3(r_ck, cz, gb[j], v34(Mo[ii[j] + nx]));
             }
         }
         // ---- 5. shift the columns; loads of plane p + 3 and axes of p + 2
@@ -221,19 +225,20 @@ __global__ __launch_bounds__(NT) void k_rows2(
         for (int j = 0; j < K; ++j) {
             qm1[j] = qn[j];
             hm1[j] = hn[j];
+            mpm2[j] = v34(Mq[ii[j]]);   // m'(p - 1), the lower neighbour of the next corrector
             B[j] = Cn[j];
             Cn[j] = Dn[j];
-            if (on[j] && p + 3 <= pz1 + 1) Dn[j] = ld(p + 3, (ii[j] + gofs));
+            if (on[j] && p + 3 <= pz1 + 1) Dn[j] = ld(p + 3, gb[j]);
             if (AXES) {
                 UA[j] = UB[j];
                 UB[j] = UC[j];
-                if (on[j] && p + 2 <= pz1) UC[j] = ldu(p + 2, (ii[j] + gofs));
+                if (on[j] && p + 2 <= pz1) UC[j] = ldu(p + 2, gb[j]);
             }
         }
         if (ex) {
             EB = EC;
             EC = ED;
-            if (p + 3 <= pz1) ED = ld(p + 3, ex_gc);
+            if (p + 3 <= pz1) ED = ld(p + 3, ex_gb);
         }
     }
 
