@@ -861,8 +861,9 @@ int slab_max_planes(const LevelHost& h)
 size_t slab_lds(const LevelHost& h)
 {
     const int mp = slab_max_planes(h);
-    const int planes = kSlabKernels[h.slab_kernel].kind == 0 ? 2 * mp + 6 : 2 * mp + 4;
-    return sizeof(float) * (size_t)planes * 3 * h.in.nx * h.in.ny;
+    // kind 0: one float4 per cell; kind 1: three float planes
+    if (kSlabKernels[h.slab_kernel].kind == 0) return 16 * (size_t)(2 * mp + 6) * h.in.nx * h.in.ny;
+    return sizeof(float) * (size_t)(2 * mp + 4) * 3 * h.in.nx * h.in.ny;
 }
 
 template <int KIND, int NT, int K>

@@ -82,7 +82,7 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
                                              double* __restrict__ partials, int pstride, float* __restrict__ ckpt,
                                              int ckpt_every, int64_t n0, int nsteps, int* __restrict__ status)
 {
-    extern __shared__ float lds[];
+    extern __shared__ float4 lds_slab[];
     __shared__ double red[NT / 64];
     __shared__ int s_abort;
 
@@ -99,9 +99,11 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
     const int x = c % nx, y = c / nx;
     const int z0 = S.z0, nzs = S.nzs;
     const int NE = nzs + 2;                     // predicted planes
-    float* Mn = lds;                            // (nzs + 4) planes x 3 x P
-    float* Mp = lds + (nzs + 4) * 3 * P;        // (nzs + 2) planes x 3 x P
-    auto mn = [&](int me, int k) -> float& { return Mn[(me * 3 + k) * P + c]; };
+    // one float4 (x, y, z, unused) per cell: one 16-byte LDS access per neighbour
+    float4* Mn = lds_slab;                      // (nzs + 4) planes of P cells
+    float4* Mp = lds_slab + (nzs + 4) * P;      // (nzs + 2) planes of P cells
+    auto f4 = [](float x, float y, float z) { return make_float4(x, y, z, 0.0f); };
+    auto v34 = [](float4 v) { return V3{v.x, v.y, v.z}; };
     const int ixm = x > 0 ? c - 1 : c, ixp = x < nx - 1 ? c + 1 : c;
     const int iym = y > 0 ? c - nx : c, iyp = y < ny - 1 ? c + nx : c;
     // exchange slot (3 x P words) of one plane of one slab at a step parity
@@ -120,9 +122,7 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
             const int z = z0 - 2 + me;
             if (!lane_on || z < 0 || z >= nz) continue;
             const int cell = c + P * z;
-            mn(me, 0) = mi[cell];
-            mn(me, 1) = mi[N + cell];
-            mn(me, 2) = mi[2 * N + cell];
+            Mn[me * P + c] = f4(mi[cell], mi[N + cell], mi[2 * N + cell]);
         }
     }
     __syncthreads();
@@ -158,22 +158,15 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
             const int z = z0 - 1 + e;
             if (!lane_on || e >= NE || z < 0 || z >= nz) continue;
             const int me = e + 1;
-            const V3 m = v3(mn(me, 0), mn(me, 1), mn(me, 2));
-            const float* pl = Mn + me * 3 * P;
-            const V3 ex = nb_sum(m, v3(pl[ixm], pl[P + ixm], pl[2 * P + ixm]),
-                                 v3(pl[ixp], pl[P + ixp], pl[2 * P + ixp]),
-                                 v3(pl[iym], pl[P + iym], pl[2 * P + iym]),
-                                 v3(pl[iyp], pl[P + iyp], pl[2 * P + iyp]),
-                                 z > 0 ? v3(mn(me - 1, 0), mn(me - 1, 1), mn(me - 1, 2)) : m,
-                                 z < nz - 1 ? v3(mn(me + 1, 0), mn(me + 1, 1), mn(me + 1, 2)) : m);
+            const float4* pl = Mn + me * P;
+            const V3 m = v34(pl[c]);
+            const V3 ex = nb_sum(m, v34(pl[ixm]), v34(pl[ixp]), v34(pl[iym]), v34(pl[iyp]),
+                                 z > 0 ? v34(pl[c - P]) : m, z < nz - 1 ? v34(pl[c + P]) : m);
             const int cell = c + P * z;
             u[j] = axes_on ? V3{ax[cell], ax[N + cell], ax[2 * N + cell]} : V3{L.ux, L.uy, L.uz};
             V3 mp;
             heun_predict(L, m, ex, u[j], hz0, hth[j], mp, q[j]);
-            float* o = Mp + e * 3 * P;
-            o[c] = mp.x;
-            o[P + c] = mp.y;
-            o[2 * P + c] = mp.z;
+            Mp[e * P + c] = f4(mp.x, mp.y, mp.z);
             if (ckpt != nullptr && ckpt_every > 0 && (n % ckpt_every) == 0 && e >= 1 && e <= nzs) {
                 float* cp = ckpt + I.ckpt_off + (n / ckpt_every) * 3 * static_cast<int64_t>(N);
                 cp[cell] = m.x;
@@ -192,21 +185,13 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
             const int e = r + j * NPP;
             if (!lane_on || e < 1 || e > nzs) continue;
             const int z = z0 - 1 + e;
-            const float* pl = Mp + e * 3 * P;
-            const V3 mp = v3(pl[c], pl[P + c], pl[2 * P + c]);
-            const float* plm = Mp + (e - 1) * 3 * P;
-            const float* plp = Mp + (e + 1) * 3 * P;
-            const V3 ex = nb_sum(mp, v3(pl[ixm], pl[P + ixm], pl[2 * P + ixm]),
-                                 v3(pl[ixp], pl[P + ixp], pl[2 * P + ixp]),
-                                 v3(pl[iym], pl[P + iym], pl[2 * P + iym]),
-                                 v3(pl[iyp], pl[P + iyp], pl[2 * P + iyp]),
-                                 z > 0 ? v3(plm[c], plm[P + c], plm[2 * P + c]) : mp,
-                                 z < nz - 1 ? v3(plp[c], plp[P + c], plp[2 * P + c]) : mp);
+            const float4* pl = Mp + e * P;
+            const V3 mp = v34(pl[c]);
+            const V3 ex = nb_sum(mp, v34(pl[ixm]), v34(pl[ixp]), v34(pl[iym]), v34(pl[iyp]),
+                                 z > 0 ? v34(pl[c - P]) : mp, z < nz - 1 ? v34(pl[c + P]) : mp);
             const V3 mnew = heun_correct(L, mp, ex, u[j], hz1, hth[j], q[j]);
             const int me = e + 1;
-            mn(me, 0) = mnew.x;
-            mn(me, 1) = mnew.y;
-            mn(me, 2) = mnew.z;
+            Mn[me * P + c] = f4(mnew.x, mnew.y, mnew.z);
             msum += mnew.z;
             // the first two and the last two planes, each once
             if (e <= 2 || e >= nzs - 1) {
@@ -251,9 +236,7 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
                 atomicOr(status, 2);
                 break;
             }
-            mn(me, 0) = word32_val(w0);
-            mn(me, 1) = word32_val(w1);
-            mn(me, 2) = word32_val(w2);
+            Mn[me * P + c] = f4(word32_val(w0), word32_val(w1), word32_val(w2));
         }
         __syncthreads();
         if (s_abort) return;
@@ -268,9 +251,10 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
     for (int me = 2 + r; me < nzs + 2; me += NPP) {
         if (!lane_on) break;
         const int cell = c + P * (z0 - 2 + me);
-        mo[cell] = mn(me, 0);
-        mo[N + cell] = mn(me, 1);
-        mo[2 * N + cell] = mn(me, 2);
+        const float4 v = Mn[me * P + c];
+        mo[cell] = v.x;
+        mo[N + cell] = v.y;
+        mo[2 * N + cell] = v.z;
     }
 }
 
