@@ -85,6 +85,7 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
     extern __shared__ float4 lds_slab[];
     __shared__ double red[NT / 64];
     __shared__ int s_abort;
+    __shared__ float s_hz[kSlabChunk + 1];   // applied field of the launch's steps
 
     const int sid = static_cast<int>(blockIdx.x);
     const SlabDev S = slabs[sid];
@@ -115,6 +116,7 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
     const int nzs_prev = S.prev >= 0 ? slabs[S.prev].nzs : 0;
     if (tid == 0) s_abort = 0;
 
+    for (int st = tid; st <= nsteps; st += NT) s_hz[st] = static_cast<float>(L.hz_amp * wave_at(L, n0 + st));
     // ---- load m_n of planes z0-2 .. z0+nzs+1 (those inside the grid)
     {
         const float* mi = ((n0 & 1) ? buf1 : buf0) + I.state_off;
@@ -143,13 +145,11 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
         }
     };
     draw(n0);
-    float hz1 = static_cast<float>(L.hz_amp * wave_at(L, n0));
     // the last wave folds the block's m_z sum of the previous step
     const bool folder = tid >= NT - 64;
     for (int st = 0; st < nsteps; ++st) {
         const int64_t n = n0 + st;
-        const float hz0 = hz1;
-        hz1 = static_cast<float>(L.hz_amp * wave_at(L, n + 1));
+        const float hz0 = s_hz[st], hz1 = s_hz[st + 1];
         V3 q[K], u[K];
         // ---- 1. predictor on planes z0-1 .. z0+nzs
 #pragma unroll
