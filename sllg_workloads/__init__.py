@@ -1,7 +1,7 @@
 """Synthetic workloads for the stochastic-LLG hysteresis-loop path.
 
 This module only *describes* inputs: the base material, the field sweep and the
-per-level grid / realization / seed settings of the five workloads below.  It
+per-level grid / realization / seed settings of the workloads below.  It
 holds none of the method's arithmetic (no coarse-graining rule, no field, no
 integrator) so that both the FP64 oracle and the HIP path can read it without
 sharing any computation.
@@ -10,8 +10,8 @@ Every workload is a magnetite rod (or block) built from cubic cells of edge
 b*a0.  The paper's rod is 8a0 x 24a0 x 56a0 with a0 = 0.839 nm (material
 paragraph, Fig. 1); coarse-graining by b gives (8/b) x (24/b) x (56/b) cells.
 Base parameters: Ms = 480 kA/m, A0 = 0.98e-11 J/m, K0 = 10 kJ/m^3 along z,
-T = 310 K, Tc = 858 K, delta = 0.511 (Eq. 13).  All sweeps are triangles that
-start at +Hmax with every moment along +z.
+T = 310 K, Tc = 858 K, delta = 0.511 (Eq. 13).  Every sweep starts at +Hmax
+with every moment along +z.
 
 Names
 -----
@@ -20,6 +20,13 @@ rod_b1_ens8        8x24x56 rod, b=1, 8 seeds, 4e6 steps of 1 fs
 multilevel_ens256  256 realizations at each of b=1,2,4,8 (1024 instances)
 block_b2_cone10    128x128x512 block, b=2, per-cell axes in a 10 degree cone
 rod_b4_adjoint64   64 realizations of the 2x6x14 b=4 rod, checkpoints every 256
+rod_sine_sr250_ens100
+                   the paper's sweep-rate/damping protocol (Fig. 4): Hmax = 500
+                   Oe, a cosine sweep at 250 Oe/ns, easy axes in a 5 degree
+                   cone, alpha = 0.1 SR/(0.25 Oe/ns) = 100, 100 realizations at
+                   b = 4 (2x6x14), b = 8 (1x3x7) and the single-cell limit
+                   (1x1x1, b = 10752^(1/3) so that the cell has the rod's
+                   volume), 5 fs steps
 """
 from __future__ import annotations
 
@@ -96,6 +103,19 @@ WORKLOADS = {
         ckpt_every=256,
     ),
 }
+
+
+# Single-cell limit of the rod: one cube with the rod's volume 10752 a0^3.
+B_SINGLE_CELL = 10752.0 ** (1.0 / 3.0)
+
+WORKLOADS["rod_sine_sr250_ens100"] = dict(
+    material=dict(BASE_MATERIAL, Hmax_Oe=500.0, sweep_Oe_per_ns=250.0, wave="cosine",
+                  sr_ref_Oe_per_ns=0.25, alpha_ref=0.1),
+    levels=[_level(*dims, b=b, alpha=0.1, dt_s=5e-15, n_real=100, seed_base=1,
+                   cone_deg=5.0, axis_seed=11, record_every=100)
+            for dims, b in (((2, 6, 14), 4), ((1, 3, 7), 8), ((1, 1, 1), B_SINGLE_CELL))],
+    ckpt_every=0,
+)
 
 
 def workload(name: str) -> dict:
