@@ -118,7 +118,12 @@ const int kTzChoices[] = {1, 2, 4, 8, 16, 32, 64};
 struct ResidentKernel {
     int nw, cpw;
 };
-const ResidentKernel kResKernels[] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {16, 1}, {16, 2}, {16, 4}, {8, 8}};
+// At most 32 chunks of 64 cells per workgroup: the step-invariant per-chunk
+// data of up to two chunks per wave stays in registers.  The planner takes
+// the first kernel whose last wave owns no chunk (it folds the loop), else
+// the first that holds every chunk.
+const ResidentKernel kResKernels[] = {{2, 1}, {4, 1}, {8, 1}, {16, 1}, {16, 2}};
+constexpr int kResMaxChunks = 32;
 
 // Layout of the workspace (byte offsets).
 struct Layout {
@@ -370,8 +375,8 @@ int resident_fits(const LevelHost& h, int max_lds)
 {
     // two AoS copies of the state plus per-chunk and per-slot bookkeeping
     const int64_t chunks = ceil_div(h.ncell, 64);
-    const int64_t bytes = 24 * h.ncell + 4 * chunks + 64 + (int64_t)sizeof(AccDev);
-    return bytes <= max_lds && chunks <= 64;
+    const int64_t bytes = 24 * h.ncell + 8 * chunks + 64 + (int64_t)sizeof(AccDev);
+    return bytes <= max_lds && chunks <= kResMaxChunks;
 }
 
 Layout make_layout(const sllg_material& m, const std::vector<LevelHost>& lv, int ckpt_every)
@@ -543,33 +548,40 @@ int build_resident(sllg_ctx* C)
             return C->lv[C->h_insts[a].level].ncell > C->lv[C->h_insts[b].level].ncell;
         });
         // number of groups: one instance per group up to two per CU, else pack
+        // (more groups while a group would exceed the chunk or LDS limit)
         int ng = (int)std::min<int64_t>(total, 2LL * C->num_cus);
         if (total > 2LL * C->num_cus) ng = C->num_cus;
-        std::vector<std::vector<int>> members(ng);
-        std::vector<int64_t> load(ng, 0), lds(ng, 0);
-        for (size_t k = 0; k < inst.size(); ++k) {
-            // round-robin over the groups (instances sorted by size)
-            int g = (int)(k % ng);
-            const LevelHost& h = C->lv[C->h_insts[inst[k]].level];
-            members[g].push_back(inst[k]);
-            load[g] += ceil_div(h.ncell, 64);
-            lds[g] += 24 * h.ncell;
-        }
+        std::vector<std::vector<int>> members;
         int64_t max_chunks = 0, max_lds = 0;
-        for (int g = 0; g < ng; ++g) {
-            max_chunks = std::max(max_chunks, load[g]);
-            max_lds = std::max<int64_t>(max_lds, lds[g] + 4 * load[g] + 32 +
-                                                     (int64_t)sizeof(AccDev) * members[g].size());
+        for (;;) {
+            members.assign(ng, {});
+            std::vector<int64_t> load(ng, 0), lds(ng, 0);
+            for (size_t k = 0; k < inst.size(); ++k) {
+                // round-robin over the groups (instances sorted by size)
+                int g = (int)(k % ng);
+                const LevelHost& h = C->lv[C->h_insts[inst[k]].level];
+                members[g].push_back(inst[k]);
+                load[g] += ceil_div(h.ncell, 64);
+                lds[g] += 24 * h.ncell;
+            }
+            max_chunks = max_lds = 0;
+            for (int g = 0; g < ng; ++g) {
+                max_chunks = std::max(max_chunks, load[g]);
+                max_lds = std::max<int64_t>(max_lds, lds[g] + 8 * load[g] + 48 +
+                                                         (int64_t)sizeof(AccDev) * members[g].size());
+            }
+            if ((max_chunks <= kResMaxChunks && max_lds <= C->max_lds) || ng >= total) break;
+            ng = (int)std::min<int64_t>(total, 2LL * ng);
         }
         if (max_lds > C->max_lds)
             return fail(SLLG_E_INVAL, "resident plan: %lld bytes of LDS per workgroup exceed %d",
                         (long long)max_lds, C->max_lds);
         int pick = -1;
-        for (int i = 0; i < (int)(sizeof(kResKernels) / sizeof(kResKernels[0])); ++i)
-            if (kResKernels[i].nw * kResKernels[i].cpw >= max_chunks) {
-                pick = i;
-                break;
-            }
+        const int nk = (int)(sizeof(kResKernels) / sizeof(kResKernels[0]));
+        for (int i = 0; i < nk && pick < 0; ++i)
+            if (kResKernels[i].cpw == 1 && kResKernels[i].nw > max_chunks) pick = i;
+        for (int i = 0; i < nk && pick < 0; ++i)
+            if (kResKernels[i].nw * kResKernels[i].cpw >= max_chunks) pick = i;
         if (pick < 0) return fail(SLLG_E_INVAL, "resident plan: %lld chunks per workgroup", (long long)max_chunks);
         rs.nw = kResKernels[pick].nw;
         rs.cpw = kResKernels[pick].cpw;
@@ -744,14 +756,11 @@ hipError_t launch_res(sllg_ctx* C, const sllg_ctx::ResSet& rs, int64_t n0, int64
 hipError_t dispatch_res(sllg_ctx* C, const sllg_ctx::ResSet& rs, int64_t n0, int64_t ns)
 {
     switch (rs.nw * 100 + rs.cpw) {
-    case 101: return launch_res<1, 1>(C, rs, n0, ns);
     case 201: return launch_res<2, 1>(C, rs, n0, ns);
     case 401: return launch_res<4, 1>(C, rs, n0, ns);
     case 801: return launch_res<8, 1>(C, rs, n0, ns);
     case 1601: return launch_res<16, 1>(C, rs, n0, ns);
     case 1602: return launch_res<16, 2>(C, rs, n0, ns);
-    case 1604: return launch_res<16, 4>(C, rs, n0, ns);
-    case 808: return launch_res<8, 8>(C, rs, n0, ns);
     default: return hipErrorInvalidValue;
     }
 }

@@ -75,12 +75,21 @@ __device__ __forceinline__ V3 load_axis(const LevelDev& L, const float* __restri
 // Resident plan.
 //
 // LDS holds two array-of-structs copies of the workgroup's state (A = m_n,
-// B = m'), 12 bytes per cell each, followed by one float per chunk for the
-// loop reduction and the slots' loop accumulators.  A wave owns up to CPW
-// chunks of 64 consecutive cells of one instance (chunk j of the workgroup
-// belongs to wave j % NW).  Per step: predictor A -> B, barrier, corrector
-// B -> A with a wave sum of m_z per chunk, barrier, one thread per slot folds
-// the chunk sums (FP64, fixed order) into the loop.
+// B = m'), 12 bytes per cell each, the chunk sums of m_z of even and odd
+// steps and the loop accumulators of the slots.  A wave owns up to CPW chunks
+// of 64 consecutive cells of one instance (chunk j of the workgroup belongs
+// to wave j % NW).  Per step: predictor A -> B, barrier, corrector B -> A
+// with a wave sum of m_z per chunk, barrier.  One thread per slot, in the
+// last wave, folds a step's chunk sums (FP64, fixed order) into the loop
+// while the other waves correct the next step, so the fold is off the
+// critical path when the last wave owns fewer chunks than the others (the
+// planner leaves it without chunks where it can).  Everything that does not
+// change with the step (the level, seed and cell of each owned chunk, the LDS
+// offsets of the cell and its neighbours, the easy axis, the slot data of
+// the folding thread) is loaded once before the step loop; the applied field
+// of step n + 1 computed for the corrector is kept for the next predictor,
+// and checkpoints are found by a countdown, so a step has no global loads
+// and no integer division on its critical path.
 // ---------------------------------------------------------------------------
 template <int NW, int CPW>
 __global__ __launch_bounds__(NW * 64) void k_resident(
@@ -94,151 +103,186 @@ __global__ __launch_bounds__(NW * 64) void k_resident(
     const GroupDev G = groups[blockIdx.x];
     float* A = lds;
     float* B = lds + 3 * G.ncells;
+    // chunk sums of even and odd steps
+    const int pstride = (G.nchunks + 3) & ~3;
     float* part = B + 3 * G.ncells;
-    AccDev* acc = reinterpret_cast<AccDev*>(part + ((G.nchunks + 3) & ~3) + 4);
+    AccDev* acc = reinterpret_cast<AccDev*>(part + 2 * pstride + 4);
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
-    // packed lane coordinates per owned chunk: x | y << 10 | z << 20 | valid << 31
-    uint32_t info[CPW];
+    // ---- per owned chunk: step-invariant data
+    const LevelDev* Lk[CPW];   // wave-uniform
+    uint64_t seed[CPW];        // wave-uniform
+    int64_t ck_off[CPW];       // wave-uniform: float offset of the instance's checkpoint 0
+    bool has[CPW];             // wave-uniform: the chunk exists
+    // per lane: the cell index, and the float offset of the cell in A / B
+    // (bits 0-15) with the existing neighbours (bits 16-21: x-1, x+1, y-1,
+    // y+1, z-1, z+1) and a valid flag (bit 31)
+    int cell[CPW];
+    uint32_t pk[CPW];
+    V3 u[CPW];
     const float* min_ = (n0 & 1) ? buf1 : buf0;
 #pragma unroll
     for (int k = 0; k < CPW; ++k) {
-        info[k] = 0u;
         const int j = wave + k * NW;
-        if (j < G.nchunks) {
-            const ChunkDev ch = chunks[G.chunk0 + j];
-            const LevelDev& L = levels[insts[ch.inst].level];
-            const int c = ch.c0 + lane;
-            if (c < L.ncell) {
-                const int x = c % L.nx, y = (c / L.nx) % L.ny, z = c / (L.nx * L.ny);
-                info[k] = static_cast<uint32_t>(x) | (static_cast<uint32_t>(y) << 10) |
-                          (static_cast<uint32_t>(z) << 20) | 0x80000000u;
-                const SlotDev S = slots[G.slot0 + ch.slot];
-                const float* src = min_ + insts[ch.inst].state_off;
-                float* d = A + 3 * (S.lds_off + c);
-                d[0] = src[c];
-                d[1] = src[L.ncell + c];
-                d[2] = src[2 * L.ncell + c];
-            }
-        }
+        has[k] = j < G.nchunks;
+        Lk[k] = levels;
+        seed[k] = 0;
+        ck_off[k] = 0;
+        cell[k] = 0;
+        pk[k] = 0u;
+        u[k] = V3{0.0f, 0.0f, 1.0f};
+        if (!has[k]) continue;
+        const ChunkDev ch = chunks[G.chunk0 + j];
+        const InstDev I = insts[ch.inst];
+        const LevelDev& L = levels[I.level];
+        const SlotDev S = slots[G.slot0 + ch.slot];
+        Lk[k] = &levels[I.level];
+        seed[k] = I.seed;
+        ck_off[k] = I.ckpt_off;
+        const int c = ch.c0 + lane;
+        if (c >= L.ncell) continue;
+        cell[k] = c;
+        const int x = c % L.nx, y = (c / L.nx) % L.ny, z = c / (L.nx * L.ny);
+        const int own = 3 * (S.lds_off + c);
+        pk[k] = static_cast<uint32_t>(own) | (x > 0 ? 1u << 16 : 0u) | (x < L.nx - 1 ? 1u << 17 : 0u) |
+                (y > 0 ? 1u << 18 : 0u) | (y < L.ny - 1 ? 1u << 19 : 0u) | (z > 0 ? 1u << 20 : 0u) |
+                (z < L.nz - 1 ? 1u << 21 : 0u) | 0x80000000u;
+        u[k] = load_axis(L, axes, c);
+        const float* src = min_ + I.state_off;
+        A[own] = src[c];
+        A[own + 1] = src[L.ncell + c];
+        A[own + 2] = src[2 * L.ncell + c];
     }
-    for (int s = threadIdx.x; s < G.nslots; s += blockDim.x) acc[s] = accs[slots[G.slot0 + s].inst];
+    // neighbour sum over the six face neighbours read from an AoS LDS copy
+    auto stencil = [&](const float* M, uint32_t p, int sy, int sz, V3 m) {
+        const int o = static_cast<int>(p & 0xFFFFu);
+        auto at = [&](int i) { return v3(M[i], M[i + 1], M[i + 2]); };
+        return nb_sum(m, at((p & (1u << 16)) ? o - 3 : o), at((p & (1u << 17)) ? o + 3 : o),
+                      at((p & (1u << 18)) ? o - sy : o), at((p & (1u << 19)) ? o + sy : o),
+                      at((p & (1u << 20)) ? o - sz : o), at((p & (1u << 21)) ? o + sz : o));
+    };
+
+    // ---- the folding thread of each slot, in the last wave (a group has at
+    // most NW * CPW <= 64 chunks, so at most one slot per thread)
+    const int fs = static_cast<int>(threadIdx.x) - (NW - 1) * 64;
+    const bool folder = fs >= 0 && fs < G.nslots;
+    const LevelDev* Lf = levels;
+    int f_chunk0 = 0, f_nchunks = 0;
+    double f_ncell = 0.0, f_h0 = 0.0;
+    double* f_rec = records;
+    int f_inst = 0;
+    if (folder) {
+        const SlotDev S = slots[G.slot0 + fs];
+        const InstDev I = insts[S.inst];
+        Lf = &levels[I.level];
+        f_inst = S.inst;
+        f_chunk0 = S.chunk0;
+        f_nchunks = S.nchunks;
+        f_ncell = static_cast<double>(Lf->ncell);
+        f_rec = records + I.rec_off;
+        f_h0 = Lf->hz_oe * wave_at(*Lf, n0);
+        acc[fs] = accs[S.inst];
+    }
+    auto fold = [&](int64_t n) {
+        // step n -> n + 1: chunk sums in a fixed order, FP64 loop update
+        const float* p = part + (n & 1) * pstride + f_chunk0;
+        double sum = 0.0;
+        for (int j = 0; j < f_nchunks; ++j) sum += static_cast<double>(p[j]);
+        const double h1 = Lf->hz_oe * wave_at(*Lf, n + 1);
+        loop_accumulate_h(acc[fs], *Lf, f_h0, h1, sum / f_ncell, f_rec);
+        f_h0 = h1;
+    };
+
+    // applied field (FP32) at the current step of each owned chunk
+    float hz[CPW];
+#pragma unroll
+    for (int k = 0; k < CPW; ++k)
+        hz[k] = has[k] ? static_cast<float>(Lk[k]->hz_amp * wave_at(*Lk[k], n0)) : 0.0f;
+    // next checkpointed step (a multiple of ckpt_every) and its index
+    const bool do_ckpt = ckpt != nullptr && ckpt_every > 0;
+    int64_t ck_idx = do_ckpt ? (n0 + ckpt_every - 1) / ckpt_every : 0;
+    int64_t ck_next = do_ckpt ? ck_idx * ckpt_every : -1;
     __syncthreads();
 
     for (int64_t st = 0; st < nsteps; ++st) {
         const int64_t n = n0 + st;
+        const bool ck_now = n == ck_next;
         V3 q[CPW], hth[CPW];
         // ---- predictor: A -> B
 #pragma unroll
         for (int k = 0; k < CPW; ++k) {
-            const int j = wave + k * NW;
-            if (j >= G.nchunks) continue;
-            const ChunkDev ch = chunks[G.chunk0 + j];
-            const InstDev I = insts[ch.inst];
-            const LevelDev& L = levels[I.level];
-            const SlotDev S = slots[G.slot0 + ch.slot];
-            if (!(info[k] & 0x80000000u)) continue;
-            const int c = ch.c0 + lane;
-            const int x = info[k] & 1023, y = (info[k] >> 10) & 1023, z = (info[k] >> 20) & 1023;
-            const int sy = L.nx, sz = L.nx * L.ny;
-            const float* a = A + 3 * S.lds_off;
-            const int ixm = (x > 0) ? c - 1 : c, ixp = (x < L.nx - 1) ? c + 1 : c;
-            const int iym = (y > 0) ? c - sy : c, iyp = (y < L.ny - 1) ? c + sy : c;
-            const int izm = (z > 0) ? c - sz : c, izp = (z < L.nz - 1) ? c + sz : c;
-            const V3 m = v3(a[3 * c], a[3 * c + 1], a[3 * c + 2]);
-            if (ckpt != nullptr && ckpt_every > 0 && (n % ckpt_every) == 0) {
-                float* cp = ckpt + I.ckpt_off + (n / ckpt_every) * 3 * L.ncell;
-                cp[c] = m.x;
-                cp[L.ncell + c] = m.y;
-                cp[2 * L.ncell + c] = m.z;
+            q[k] = hth[k] = V3{0.0f, 0.0f, 0.0f};
+            if (!has[k] || !(pk[k] & 0x80000000u)) continue;
+            const LevelDev& L = *Lk[k];
+            const int own = static_cast<int>(pk[k] & 0xFFFFu);
+            const V3 m = v3(A[own], A[own + 1], A[own + 2]);
+            if (ck_now) {
+                float* cp = ckpt + ck_off[k] + ck_idx * 3 * L.ncell;
+                cp[cell[k]] = m.x;
+                cp[L.ncell + cell[k]] = m.y;
+                cp[2 * L.ncell + cell[k]] = m.z;
             }
-            const V3 ex = nb_sum(m, v3(a[3 * ixm], a[3 * ixm + 1], a[3 * ixm + 2]),
-                                 v3(a[3 * ixp], a[3 * ixp + 1], a[3 * ixp + 2]),
-                                 v3(a[3 * iym], a[3 * iym + 1], a[3 * iym + 2]),
-                                 v3(a[3 * iyp], a[3 * iyp + 1], a[3 * iyp + 2]),
-                                 v3(a[3 * izm], a[3 * izm + 1], a[3 * izm + 2]),
-                                 v3(a[3 * izp], a[3 * izp + 1], a[3 * izp + 2]));
-            const float hz = static_cast<float>(L.hz_amp * wave_at(L, n));
-            hth[k] = thermal_field(L, I.seed, static_cast<uint32_t>(c), n);
+            const V3 ex = stencil(A, pk[k], 3 * L.nx, 3 * L.nx * L.ny, m);
+            hth[k] = thermal_field(L, seed[k], static_cast<uint32_t>(cell[k]), n);
             V3 mp;
-            heun_predict(L, m, ex, load_axis(L, axes, c), hz, hth[k], mp, q[k]);
-            float* b = B + 3 * (S.lds_off + c);
-            b[0] = mp.x;
-            b[1] = mp.y;
-            b[2] = mp.z;
+            heun_predict(L, m, ex, L.has_axes ? u[k] : V3{L.ux, L.uy, L.uz}, hz[k], hth[k], mp, q[k]);
+            B[own] = mp.x;
+            B[own + 1] = mp.y;
+            B[own + 2] = mp.z;
         }
         __syncthreads();
+        // ---- fold of the previous step (its chunk sums are in the other buffer)
+        if (folder && st > 0) fold(n - 1);
         // ---- corrector: B -> A, wave sums of m_z per chunk
 #pragma unroll
         for (int k = 0; k < CPW; ++k) {
-            const int j = wave + k * NW;
-            if (j >= G.nchunks) continue;
-            const ChunkDev ch = chunks[G.chunk0 + j];
-            const InstDev I = insts[ch.inst];
-            const LevelDev& L = levels[I.level];
-            const SlotDev S = slots[G.slot0 + ch.slot];
+            if (!has[k]) continue;
+            const LevelDev& L = *Lk[k];
+            const float hz1 = static_cast<float>(L.hz_amp * wave_at(L, n + 1));
             float mz = 0.0f;
-            if (info[k] & 0x80000000u) {
-                const int c = ch.c0 + lane;
-                const int x = info[k] & 1023, y = (info[k] >> 10) & 1023, z = (info[k] >> 20) & 1023;
-                const int sy = L.nx, sz = L.nx * L.ny;
-                const float* b = B + 3 * S.lds_off;
-                const int ixm = (x > 0) ? c - 1 : c, ixp = (x < L.nx - 1) ? c + 1 : c;
-                const int iym = (y > 0) ? c - sy : c, iyp = (y < L.ny - 1) ? c + sy : c;
-                const int izm = (z > 0) ? c - sz : c, izp = (z < L.nz - 1) ? c + sz : c;
-                const V3 mp = v3(b[3 * c], b[3 * c + 1], b[3 * c + 2]);
-                const V3 ex = nb_sum(mp, v3(b[3 * ixm], b[3 * ixm + 1], b[3 * ixm + 2]),
-                                     v3(b[3 * ixp], b[3 * ixp + 1], b[3 * ixp + 2]),
-                                     v3(b[3 * iym], b[3 * iym + 1], b[3 * iym + 2]),
-                                     v3(b[3 * iyp], b[3 * iyp + 1], b[3 * iyp + 2]),
-                                     v3(b[3 * izm], b[3 * izm + 1], b[3 * izm + 2]),
-                                     v3(b[3 * izp], b[3 * izp + 1], b[3 * izp + 2]));
-                const float hz1 = static_cast<float>(L.hz_amp * wave_at(L, n + 1));
-                const V3 mn = heun_correct(L, mp, ex, load_axis(L, axes, c), hz1, hth[k], q[k]);
-                float* a = A + 3 * (S.lds_off + c);
-                a[0] = mn.x;
-                a[1] = mn.y;
-                a[2] = mn.z;
+            if (pk[k] & 0x80000000u) {
+                const int own = static_cast<int>(pk[k] & 0xFFFFu);
+                const V3 mp = v3(B[own], B[own + 1], B[own + 2]);
+                const V3 ex = stencil(B, pk[k], 3 * L.nx, 3 * L.nx * L.ny, mp);
+                const V3 mn = heun_correct(L, mp, ex, L.has_axes ? u[k] : V3{L.ux, L.uy, L.uz}, hz1, hth[k],
+                                           q[k]);
+                A[own] = mn.x;
+                A[own + 1] = mn.y;
+                A[own + 2] = mn.z;
                 mz = mn.z;
             }
+            hz[k] = hz1;
             const float ps = wave_sum(mz);
-            if (lane == 0) part[j] = ps;
+            if (lane == 0) part[(n & 1) * pstride + wave + k * NW] = ps;
         }
         __syncthreads();
-        // ---- loop reduction, one thread per slot, fixed order
-        for (int s = threadIdx.x; s < G.nslots; s += blockDim.x) {
-            const SlotDev S = slots[G.slot0 + s];
-            const InstDev I = insts[S.inst];
-            const LevelDev& L = levels[I.level];
-            double sum = 0.0;
-            for (int j = 0; j < S.nchunks; ++j) sum += static_cast<double>(part[S.chunk0 + j]);
-            loop_accumulate(acc[s], L, n, sum / static_cast<double>(L.ncell), records + I.rec_off);
+        if (ck_now) {
+            ck_next += ckpt_every;
+            ++ck_idx;
         }
         // the next predictor only reads A, the next corrector writes A after a barrier
     }
+    if (folder && nsteps > 0) fold(n0 + nsteps - 1);
     __syncthreads();
     // write back state (buffer (n0 + nsteps) & 1) and accumulators
     float* mout = ((n0 + nsteps) & 1) ? buf1 : buf0;
 #pragma unroll
     for (int k = 0; k < CPW; ++k) {
+        if (!has[k] || !(pk[k] & 0x80000000u)) continue;
         const int j = wave + k * NW;
-        if (j >= G.nchunks) continue;
         const ChunkDev ch = chunks[G.chunk0 + j];
-        const LevelDev& L = levels[insts[ch.inst].level];
-        const SlotDev S = slots[G.slot0 + ch.slot];
-        if (!(info[k] & 0x80000000u)) continue;
-        const int c = ch.c0 + lane;
-        const float* a = A + 3 * (S.lds_off + c);
+        const int N = Lk[k]->ncell;
+        const int own = static_cast<int>(pk[k] & 0xFFFFu);
         float* d = mout + insts[ch.inst].state_off;
-        d[c] = a[0];
-        d[L.ncell + c] = a[1];
-        d[2 * L.ncell + c] = a[2];
+        d[cell[k]] = A[own];
+        d[N + cell[k]] = A[own + 1];
+        d[2 * N + cell[k]] = A[own + 2];
     }
-    for (int s = threadIdx.x; s < G.nslots; s += blockDim.x) {
-        const AccDev a = acc[s];
-        accs[slots[G.slot0 + s].inst] = a;
+    if (folder) {
+        const AccDev a = acc[fs];
+        accs[f_inst] = a;
         if (!isfinite(a.m_prev)) atomicOr(status, 1);
     }
 }
