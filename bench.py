@@ -11,7 +11,9 @@ in HBM when timing starts.  Rank 0 prints one JSON line.
 
 Workloads (sllg_workloads): rod_b1_ens8 (default: 8x24x56 rod, b=1, 8
 realizations, 4e6 steps of 1 fs), rod_b4_single, multilevel_ens256,
-block_b2_cone10, rod_b4_adjoint64.
+block_b2_cone10, rod_b4_adjoint64, and the paper's protocol
+rod_sine_sr250_ens100 and rod_sine_sr2p5_ens100 (a sweep of 1.6e8 steps:
+run it with --steps 1 --warmup 0).
 """
 from __future__ import annotations
 
@@ -43,6 +45,8 @@ PEAK_HBM_GBS = 8000.0
 # FP32 vector peak 157.3 TFLOP/s = 78.6e12 FMA lane-operations per second
 # (256 CUs x 128 lanes x 2.4 GHz); one VALU op per lane counted as one
 PEAK_VALU_TOPS = 256 * 128 * 2.4e9 / 1e12
+# sweeps longer than this many steps run in pieces that report progress
+LONG_SWEEP = 20_000_000
 
 
 def parse():
@@ -99,7 +103,17 @@ def main():
     def one_step():
         # one sweep (or window) of every level and realization
         t = time.perf_counter()
-        if window == n_sweep:
+        if window == n_sweep and n_sweep > LONG_SWEEP:
+            # a sweep of minutes: the same steps in pieces, with progress
+            sim.reset()
+            done = 0
+            while done < n_sweep:
+                k = min(LONG_SWEEP, n_sweep - done)
+                sim.run_steps(k)
+                done += k
+                sim.synchronize()
+                print(f"  {done}/{n_sweep} Heun steps", file=sys.stderr, flush=True)
+        elif window == n_sweep:
             sim.reset()
             sim.run_sweep()
         else:
@@ -117,8 +131,9 @@ def main():
 
     if "window" in wl and window < n_sweep:
         sim.run_steps(wl["window"]["warmup_steps"])
-    for _ in range(warmup):
+    for i in range(warmup):
         one_step()
+        print(f"warmup step {i + 1}/{warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_split["forward"] = t_split["grad"] = 0.0
     # HIP events on the library's stream around the dominant kernel's launch
@@ -127,8 +142,10 @@ def main():
     sim.set_timing(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for i in range(steps):
         one_step()
+        # progress on stderr (microseconds against sweeps of seconds)
+        print(f"timed step {i + 1}/{steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     k_ms, k_n, k_cells = sim.kernel_time()

@@ -34,6 +34,12 @@ struct U4 {
     uint32_t a, b, c, d;
 };
 
+// Three-input exclusive or in one gfx950 VALU instruction (truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ U4 philox10(U4 w, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
@@ -41,9 +47,16 @@ __device__ __forceinline__ U4 philox10(U4 w, uint32_t k0, uint32_t k1)
         const uint64_t p = static_cast<uint64_t>(0xD2511F53u) * w.a;
         const uint64_t s = static_cast<uint64_t>(0xCD9E8D57u) * w.c;
         U4 n;
-        n.a = static_cast<uint32_t>(s >> 32) ^ w.b ^ k0;
+        if (r < 2) {
+            // the first rounds mix wave-uniform counter words (step, tags),
+            // which plain operators keep on the scalar unit
+            n.a = static_cast<uint32_t>(s >> 32) ^ w.b ^ k0;
+            n.c = static_cast<uint32_t>(p >> 32) ^ w.d ^ k1;
+        } else {
+            n.a = xor3(static_cast<uint32_t>(s >> 32), w.b, k0);
+            n.c = xor3(static_cast<uint32_t>(p >> 32), w.d, k1);
+        }
         n.b = static_cast<uint32_t>(s);
-        n.c = static_cast<uint32_t>(p >> 32) ^ w.d ^ k1;
         n.d = static_cast<uint32_t>(p);
         w = n;
         k0 += 0x9E3779B9u;
@@ -218,7 +231,7 @@ __device__ inline void loop_accumulate(AccDev& a, const LevelDev& L, int64_t n, 
     loop_accumulate_h(a, L, L.hz_oe * wave_at(L, n), L.hz_oe * wave_at(L, n + 1), m_new, rec);
 }
 
-// Wave-wide FP32 sum (all 64 lanes end with the total).
+// Wave-wide FP32 sum (every lane gets the total).
 __device__ __forceinline__ float wave_sum(float v);
 __device__ __forceinline__ double wave_sum_d(double v);
 
@@ -274,11 +287,27 @@ __device__ inline void stream_block_end(double tot, int64_t n, int tile, int pti
         if (n + 1 <= n_steps) __hip_atomic_store(&steps[level], n + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
+// DPP lane move (data-parallel primitive; lanes that receive nothing get 0)
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ float dpp_mov(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, true));
+}
+
+// Wave-wide FP32 sum in a fixed order without the LDS crossbar: pairs and
+// quads (quad permutes), half rows and rows (mirrors), then rows 0+1 and
+// 2+3 (broadcast of lane 15) and all four (broadcast of lane 31); lane 63
+// ends with the total, which is returned to every lane.  Called with every
+// lane of the wave active.
 __device__ __forceinline__ float wave_sum(float v)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_mov<0xB1>(v);          // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);          // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);         // row_half_mirror
+    v += dpp_mov<0x140>(v);         // row_mirror
+    v += dpp_mov<0x142, 0xA>(v);    // row_bcast:15 into rows 1 and 3
+    v += dpp_mov<0x143, 0xC>(v);    // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 __device__ __forceinline__ double wave_sum_d(double v)

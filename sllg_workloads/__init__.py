@@ -27,6 +27,11 @@ rod_sine_sr250_ens100
                    b = 4 (2x6x14), b = 8 (1x3x7) and the single-cell limit
                    (1x1x1, b = 10752^(1/3) so that the cell has the rod's
                    volume), 5 fs steps
+rod_sine_sr2p5_ens100
+                   the same rod levels at 2.5 Oe/ns with alpha = 0.1 (the
+                   conditions of the cell-size figure, Fig. 2) and alpha = 1
+                   (SR/alpha = 2.5 Oe/ns, Fig. 4), 100 realizations each,
+                   1.6e8 steps of 5 fs: the comparison with the printed areas
 """
 from __future__ import annotations
 
@@ -113,6 +118,16 @@ WORKLOADS["rod_sine_sr250_ens100"] = dict(
                   sr_ref_Oe_per_ns=0.25, alpha_ref=0.1),
     levels=[_level(*dims, b=b, alpha=0.1, dt_s=5e-15, n_real=100, seed_base=1,
                    cone_deg=5.0, axis_seed=11, record_every=100)
+            for dims, b in (((2, 6, 14), 4), ((1, 3, 7), 8), ((1, 1, 1), B_SINGLE_CELL))],
+    ckpt_every=0,
+)
+
+
+WORKLOADS["rod_sine_sr2p5_ens100"] = dict(
+    material=dict(BASE_MATERIAL, Hmax_Oe=500.0, sweep_Oe_per_ns=2.5, wave="cosine"),
+    levels=[_level(*dims, b=b, alpha=alpha, dt_s=5e-15, n_real=100, seed_base=1,
+                   cone_deg=5.0, axis_seed=11, record_every=1000)
+            for alpha in (0.1, 1.0)
             for dims, b in (((2, 6, 14), 4), ((1, 3, 7), 8), ((1, 1, 1), B_SINGLE_CELL))],
     ckpt_every=0,
 )
