@@ -190,7 +190,9 @@ __device__ inline double zero_field_ordinate(double h0, double dH, double m0, do
     return m0 + (m1 - m0) * (0.0 - h0) / dH;
 }
 
-// h0, h1: simulated field (Oe) at steps n and n + 1.
+// h0, h1: simulated field (Oe) at steps n and n + 1.  Written with selects
+// rather than stores in branches, so that a copy of the accumulators can
+// live in registers.
 __device__ inline void loop_accumulate_h(AccDev& a, const LevelDev& L, double h0, double h1, double m_new,
                                          double* rec)
 {
@@ -198,27 +200,27 @@ __device__ inline void loop_accumulate_h(AccDev& a, const LevelDev& L, double h0
     const double m0 = a.m_prev;
     a.area -= 0.5 * (m0 + m_new) * dH;
     const int change = (m0 > 0.0) != (m_new > 0.0);
-    if (dH < 0.0) {
-        a.ncross_d += change;
-        if (!a.found_d && m0 > 0.0 && m_new <= 0.0) {
-            a.found_d = 1;
-            a.hstar_d = cross_field(h0, dH, m0, m_new);
-        }
-        if (!a.found0_d && h0 > 0.0 && h1 <= 0.0) {
-            a.found0_d = 1;
-            a.m0_d = zero_field_ordinate(h0, dH, m0, m_new);
-        }
-    } else if (dH > 0.0) {
-        a.ncross_a += change;
-        if (!a.found_a && m0 < 0.0 && m_new >= 0.0) {
-            a.found_a = 1;
-            a.hstar_a = cross_field(h0, dH, m0, m_new);
-        }
-        if (!a.found0_a && h0 < 0.0 && h1 >= 0.0) {
-            a.found0_a = 1;
-            a.m0_a = zero_field_ordinate(h0, dH, m0, m_new);
-        }
-    }
+    const bool fall = dH < 0.0, rise = dH > 0.0;
+    a.ncross_d += fall ? change : 0;
+    a.ncross_a += rise ? change : 0;
+    // first crossing of the ordinate through zero on each branch
+    const bool hit_d = fall && !a.found_d && m0 > 0.0 && m_new <= 0.0;
+    const bool hit_a = rise && !a.found_a && m0 < 0.0 && m_new >= 0.0;
+    double xf = 0.0;
+    if (hit_d || hit_a) xf = cross_field(h0, dH, m0, m_new);
+    a.hstar_d = hit_d ? xf : a.hstar_d;
+    a.hstar_a = hit_a ? xf : a.hstar_a;
+    a.found_d |= hit_d ? 1 : 0;
+    a.found_a |= hit_a ? 1 : 0;
+    // ordinate where the field crosses zero on each branch
+    const bool z_d = fall && !a.found0_d && h0 > 0.0 && h1 <= 0.0;
+    const bool z_a = rise && !a.found0_a && h0 < 0.0 && h1 >= 0.0;
+    double zf = 0.0;
+    if (z_d || z_a) zf = zero_field_ordinate(h0, dH, m0, m_new);
+    a.m0_d = z_d ? zf : a.m0_d;
+    a.m0_a = z_a ? zf : a.m0_a;
+    a.found0_d |= z_d ? 1 : 0;
+    a.found0_a |= z_a ? 1 : 0;
     a.m_prev = m_new;
     if (++a.rec_phase == L.record_every) {
         a.rec_phase = 0;

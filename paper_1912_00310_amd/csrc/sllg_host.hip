@@ -375,7 +375,7 @@ int resident_fits(const LevelHost& h, int max_lds)
 {
     // two AoS copies of the state plus per-chunk and per-slot bookkeeping
     const int64_t chunks = ceil_div(h.ncell, 64);
-    const int64_t bytes = 24 * h.ncell + 8 * chunks + 64 + (int64_t)sizeof(AccDev);
+    const int64_t bytes = 24 * h.ncell + 8 * chunks + 64 + (int64_t)sizeof(AccDev) + 16;
     return bytes <= max_lds && chunks <= kResMaxChunks;
 }
 
@@ -568,7 +568,7 @@ int build_resident(sllg_ctx* C)
             for (int g = 0; g < ng; ++g) {
                 max_chunks = std::max(max_chunks, load[g]);
                 max_lds = std::max<int64_t>(max_lds, lds[g] + 8 * load[g] + 48 +
-                                                         (int64_t)sizeof(AccDev) * members[g].size());
+                                                         (int64_t)(sizeof(AccDev) + 16) * members[g].size());
             }
             if ((max_chunks <= kResMaxChunks && max_lds <= C->max_lds) || ng >= total) break;
             ng = (int)std::min<int64_t>(total, 2LL * ng);

@@ -76,20 +76,20 @@ __device__ __forceinline__ V3 load_axis(const LevelDev& L, const float* __restri
 //
 // LDS holds two array-of-structs copies of the workgroup's state (A = m_n,
 // B = m'), 12 bytes per cell each, the chunk sums of m_z of even and odd
-// steps and the loop accumulators of the slots.  A wave owns up to CPW chunks
-// of 64 consecutive cells of one instance (chunk j of the workgroup belongs
-// to wave j % NW).  Per step: predictor A -> B, barrier, corrector B -> A
-// with a wave sum of m_z per chunk, barrier.  One thread per slot, in the
-// last wave, folds a step's chunk sums (FP64, fixed order) into the loop
-// while the other waves correct the next step, so the fold is off the
-// critical path when the last wave owns fewer chunks than the others (the
-// planner leaves it without chunks where it can).  Everything that does not
-// change with the step (the level, seed and cell of each owned chunk, the LDS
-// offsets of the cell and its neighbours, the easy axis, the slot data of
-// the folding thread) is loaded once before the step loop; the applied field
-// of step n + 1 computed for the corrector is kept for the next predictor,
-// and checkpoints are found by a countdown, so a step has no global loads
-// and no integer division on its critical path.
+// steps, the loop accumulators of the slots and a ring of applied fields per
+// slot.  A wave owns up to CPW chunks of 64 consecutive cells of one instance
+// (chunk j of the workgroup belongs to wave j % NW).  Per step: predictor
+// A -> B, barrier, corrector B -> A with a wave sum of m_z per chunk,
+// barrier.  One thread per slot, in the last wave, folds a step's chunk sums
+// (FP64, fixed order) into the loop during the next step and computes the
+// applied field two steps ahead, so this work is off the critical path when
+// the last wave owns fewer chunks than the others (the planner leaves it
+// without chunks where it can).  Everything that does not change with the
+// step (the level, seed and cell of each owned chunk, the LDS offsets of the
+// cell and its neighbours, the easy axis, the slot data of the folding
+// thread) is loaded once before the step loop, and checkpoints are found by
+// a countdown, so a step has no global loads, no FP64 and no integer
+// division on the critical path of the waves that own cells.
 // ---------------------------------------------------------------------------
 template <int NW, int CPW>
 __global__ __launch_bounds__(NW * 64) void k_resident(
@@ -107,12 +107,15 @@ __global__ __launch_bounds__(NW * 64) void k_resident(
     const int pstride = (G.nchunks + 3) & ~3;
     float* part = B + 3 * G.ncells;
     AccDev* acc = reinterpret_cast<AccDev*>(part + 2 * pstride + 4);
+    // applied field (FP32) per slot for steps n + 1 .. n + 2, a ring of four
+    float* s_hz = reinterpret_cast<float*>(acc + G.nslots);
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
     // ---- per owned chunk: step-invariant data
     const LevelDev* Lk[CPW];   // wave-uniform
+    int slot[CPW];             // wave-uniform
     uint64_t seed[CPW];        // wave-uniform
     int64_t ck_off[CPW];       // wave-uniform: float offset of the instance's checkpoint 0
     bool has[CPW];             // wave-uniform: the chunk exists
@@ -128,6 +131,7 @@ __global__ __launch_bounds__(NW * 64) void k_resident(
         const int j = wave + k * NW;
         has[k] = j < G.nchunks;
         Lk[k] = levels;
+        slot[k] = 0;
         seed[k] = 0;
         ck_off[k] = 0;
         cell[k] = 0;
@@ -139,6 +143,7 @@ __global__ __launch_bounds__(NW * 64) void k_resident(
         const LevelDev& L = levels[I.level];
         const SlotDev S = slots[G.slot0 + ch.slot];
         Lk[k] = &levels[I.level];
+        slot[k] = ch.slot;
         seed[k] = I.seed;
         ck_off[k] = I.ckpt_off;
         const int c = ch.c0 + lane;
@@ -168,31 +173,46 @@ __global__ __launch_bounds__(NW * 64) void k_resident(
     // most NW * CPW <= 64 chunks, so at most one slot per thread)
     const int fs = static_cast<int>(threadIdx.x) - (NW - 1) * 64;
     const bool folder = fs >= 0 && fs < G.nslots;
-    const LevelDev* Lf = levels;
+    // the folding thread's level by value: the fields the fold reads stay in
+    // registers (a per-thread pointer would be a vector load every step)
+    LevelDev Lf{};
     int f_chunk0 = 0, f_nchunks = 0;
-    double f_ncell = 0.0, f_h0 = 0.0;
+    double f_ncell = 0.0;
+    double H0 = 0.0, H1 = 0.0, H2 = 0.0;   // applied field (Oe) at steps n - 1, n, n + 1 of step n
     double* f_rec = records;
     int f_inst = 0;
     if (folder) {
         const SlotDev S = slots[G.slot0 + fs];
         const InstDev I = insts[S.inst];
-        Lf = &levels[I.level];
+        Lf = levels[I.level];
         f_inst = S.inst;
         f_chunk0 = S.chunk0;
         f_nchunks = S.nchunks;
-        f_ncell = static_cast<double>(Lf->ncell);
+        f_ncell = static_cast<double>(Lf.ncell);
         f_rec = records + I.rec_off;
-        f_h0 = Lf->hz_oe * wave_at(*Lf, n0);
+        H1 = Lf.hz_oe * wave_at(Lf, n0);
+        const double w = wave_at(Lf, n0 + 1);
+        H2 = Lf.hz_oe * w;
+        s_hz[4 * fs + ((n0 + 1) & 3)] = static_cast<float>(Lf.hz_amp * w);
         acc[fs] = accs[S.inst];
     }
-    auto fold = [&](int64_t n) {
-        // step n -> n + 1: chunk sums in a fixed order, FP64 loop update
-        const float* p = part + (n & 1) * pstride + f_chunk0;
+    // The folding thread splits its work over the two phases of step n:
+    // while the other waves predict, the loop ordinate of step n (from the
+    // chunk sums of step n - 1, in a fixed order) and the applied field of
+    // step n + 2 for the correctors of step n + 1; while they correct, the
+    // FP64 loop update of step n - 1 -> n.  H0, H1, H2 hold the applied field
+    // (Oe) at steps n - 1, n, n + 1.
+    double m_fold = 0.0, H3 = 0.0;
+    auto ordinate = [&](int64_t m) {
+        const float* p = part + (m & 1) * pstride + f_chunk0;
         double sum = 0.0;
         for (int j = 0; j < f_nchunks; ++j) sum += static_cast<double>(p[j]);
-        const double h1 = Lf->hz_oe * wave_at(*Lf, n + 1);
-        loop_accumulate_h(acc[fs], *Lf, f_h0, h1, sum / f_ncell, f_rec);
-        f_h0 = h1;
+        m_fold = sum / f_ncell;
+    };
+    auto field_ahead = [&](int64_t n) {
+        const double w = wave_at(Lf, n + 2);
+        s_hz[4 * fs + ((n + 2) & 3)] = static_cast<float>(Lf.hz_amp * w);
+        H3 = Lf.hz_oe * w;
     };
 
     // applied field (FP32) at the current step of each owned chunk
@@ -210,6 +230,11 @@ __global__ __launch_bounds__(NW * 64) void k_resident(
         const int64_t n = n0 + st;
         const bool ck_now = n == ck_next;
         V3 q[CPW], hth[CPW];
+        // ---- loop ordinate of the previous step, field ahead
+        if (folder) {
+            if (st > 0) ordinate(n - 1);
+            field_ahead(n);
+        }
         // ---- predictor: A -> B
 #pragma unroll
         for (int k = 0; k < CPW; ++k) {
@@ -233,14 +258,19 @@ __global__ __launch_bounds__(NW * 64) void k_resident(
             B[own + 2] = mp.z;
         }
         __syncthreads();
-        // ---- fold of the previous step (its chunk sums are in the other buffer)
-        if (folder && st > 0) fold(n - 1);
+        // ---- loop update of the previous step
+        if (folder) {
+            if (st > 0) loop_accumulate_h(acc[fs], Lf, H0, H1, m_fold, f_rec);
+            H0 = H1;
+            H1 = H2;
+            H2 = H3;
+        }
         // ---- corrector: B -> A, wave sums of m_z per chunk
 #pragma unroll
         for (int k = 0; k < CPW; ++k) {
             if (!has[k]) continue;
             const LevelDev& L = *Lk[k];
-            const float hz1 = static_cast<float>(L.hz_amp * wave_at(L, n + 1));
+            const float hz1 = s_hz[4 * slot[k] + ((n + 1) & 3)];
             float mz = 0.0f;
             if (pk[k] & 0x80000000u) {
                 const int own = static_cast<int>(pk[k] & 0xFFFFu);
@@ -264,7 +294,10 @@ __global__ __launch_bounds__(NW * 64) void k_resident(
         }
         // the next predictor only reads A, the next corrector writes A after a barrier
     }
-    if (folder && nsteps > 0) fold(n0 + nsteps - 1);
+    if (folder && nsteps > 0) {
+        ordinate(n0 + nsteps - 1);
+        loop_accumulate_h(acc[fs], Lf, H0, H1, m_fold, f_rec);
+    }
     __syncthreads();
     // write back state (buffer (n0 + nsteps) & 1) and accumulators
     float* mout = ((n0 + nsteps) & 1) ? buf1 : buf0;
