@@ -552,7 +552,7 @@ int build_resident(sllg_ctx* C)
         int ng = (int)std::min<int64_t>(total, 2LL * C->num_cus);
         if (total > 2LL * C->num_cus) ng = C->num_cus;
         std::vector<std::vector<int>> members;
-        int64_t max_chunks = 0, max_lds = 0;
+        int64_t max_chunks = 0, max_lds = 0, max_cells = 0;
         for (;;) {
             members.assign(ng, {});
             std::vector<int64_t> load(ng, 0), lds(ng, 0);
@@ -564,9 +564,10 @@ int build_resident(sllg_ctx* C)
                 load[g] += ceil_div(h.ncell, 64);
                 lds[g] += 24 * h.ncell;
             }
-            max_chunks = max_lds = 0;
+            max_chunks = max_lds = max_cells = 0;
             for (int g = 0; g < ng; ++g) {
                 max_chunks = std::max(max_chunks, load[g]);
+                max_cells = std::max(max_cells, lds[g] / 24);
                 max_lds = std::max<int64_t>(max_lds, lds[g] + 8 * load[g] + 48 +
                                                          (int64_t)(sizeof(AccDev) + 16) * members[g].size());
             }
@@ -617,6 +618,9 @@ int build_resident(sllg_ctx* C)
             C->h_groups.push_back(G);
         }
         rs.lds = (size_t)max_lds + 64;
+        // kernels with noise waves (NW <= 8, at most 7 chunks) also hold the
+        // thermal field of two steps: 24 bytes per cell
+        if (rs.nw <= 8) rs.lds += (size_t)(24 * max_cells);
         C->res_sets.push_back(rs);
     }
     return SLLG_OK;
@@ -746,7 +750,7 @@ hipError_t launch_res(sllg_ctx* C, const sllg_ctx::ResSet& rs, int64_t n0, int64
     const size_t lds = rs.lds;
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_resident<NW, CPW>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_resident<NW, CPW>), dim3(rs.ngroups), dim3(NW * 64), lds, C->stream,
+    hipLaunchKernelGGL((k_resident<NW, CPW>), dim3(rs.ngroups), dim3(kResThreads<NW>), lds, C->stream,
                        C->d_groups + rs.group0, C->d_slots, C->d_chunks, C->d_insts, C->d_levels,
                        C->d_buf0, C->d_buf1, C->d_axes, C->d_records, C->d_accs, C->d_ckpt,
                        C->ckpt_every, n0, ns, C->d_status);

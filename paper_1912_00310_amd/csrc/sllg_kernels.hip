@@ -91,8 +91,27 @@ __device__ __forceinline__ V3 load_axis(const LevelDev& L, const float* __restri
 // a countdown, so a step has no global loads, no FP64 and no integer
 // division on the critical path of the waves that own cells.
 // ---------------------------------------------------------------------------
+// A copy of a wave-uniform value in a vector register: the compiler cannot
+// re-read it from memory inside a loop (a scalar reload waits on the same
+// counter as the LDS reads of the step).
+__device__ __forceinline__ float vreg(float x)
+{
+    float r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// With NW <= 8 the workgroup has NW more waves: wave NW + w draws the
+// thermal field of step n + 1 for the cells of wave w into an LDS buffer
+// (two step parities) while the cell waves predict step n, so Philox and
+// Box-Muller leave the cell waves' chain.
+template <int NW>
+constexpr bool kNoiseWaves = NW <= 8;
+template <int NW>
+constexpr int kResThreads = (kNoiseWaves<NW> ? 2 : 1) * NW * 64;
+
 template <int NW, int CPW>
-__global__ __launch_bounds__(NW * 64) void k_resident(
+__global__ __launch_bounds__(kResThreads<NW>) void k_resident(
     const GroupDev* __restrict__ groups, const SlotDev* __restrict__ slots,
     const ChunkDev* __restrict__ chunks, const InstDev* __restrict__ insts,
     const LevelDev* __restrict__ levels, float* __restrict__ buf0, float* __restrict__ buf1,
@@ -101,17 +120,22 @@ __global__ __launch_bounds__(NW * 64) void k_resident(
 {
     extern __shared__ float lds[];
     const GroupDev G = groups[blockIdx.x];
+    constexpr bool NP = kNoiseWaves<NW>;
     float* A = lds;
     float* B = lds + 3 * G.ncells;
+    // thermal field of even and odd steps (noise waves only)
+    float* T = B + 3 * G.ncells;
     // chunk sums of even and odd steps
     const int pstride = (G.nchunks + 3) & ~3;
-    float* part = B + 3 * G.ncells;
+    float* part = T + (NP ? 6 * G.ncells : 0);
     AccDev* acc = reinterpret_cast<AccDev*>(part + 2 * pstride + 4);
     // applied field (FP32) per slot for steps n + 1 .. n + 2, a ring of four
     float* s_hz = reinterpret_cast<float*>(acc + G.nslots);
 
     const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int w_id = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool noise_wave = NP && w_id >= NW;
+    const int wave = noise_wave ? w_id - NW : w_id;   // the cell wave whose chunks this wave serves
 
     // ---- per owned chunk: step-invariant data
     const LevelDev* Lk[CPW];   // wave-uniform
@@ -125,6 +149,9 @@ __global__ __launch_bounds__(NW * 64) void k_resident(
     int cell[CPW];
     uint32_t pk[CPW];
     V3 u[CPW];
+    // the step constants of each chunk's level, held in vector registers
+    LevelDev Lc[CPW];
+    int sy[CPW], sz[CPW];
     const float* min_ = (n0 & 1) ? buf1 : buf0;
 #pragma unroll
     for (int k = 0; k < CPW; ++k) {
@@ -137,12 +164,24 @@ __global__ __launch_bounds__(NW * 64) void k_resident(
         cell[k] = 0;
         pk[k] = 0u;
         u[k] = V3{0.0f, 0.0f, 1.0f};
+        Lc[k] = LevelDev{};
+        sy[k] = sz[k] = 0;
         if (!has[k]) continue;
         const ChunkDev ch = chunks[G.chunk0 + j];
         const InstDev I = insts[ch.inst];
         const LevelDev& L = levels[I.level];
         const SlotDev S = slots[G.slot0 + ch.slot];
         Lk[k] = &levels[I.level];
+        // (with two chunks per wave the registers are needed elsewhere)
+        auto keep = [](float x) { return CPW == 1 ? vreg(x) : x; };
+        Lc[k].c_ex = keep(L.c_ex);
+        Lc[k].hk = keep(L.hk);
+        Lc[k].g1 = keep(L.g1);
+        Lc[k].ag1 = keep(L.ag1);
+        Lc[k].dt = keep(L.dt);
+        Lc[k].half_dt = keep(L.half_dt);
+        sy[k] = __float_as_int(keep(__int_as_float(3 * L.nx)));
+        sz[k] = __float_as_int(keep(__int_as_float(3 * L.nx * L.ny)));
         slot[k] = ch.slot;
         seed[k] = I.seed;
         ck_off[k] = I.ckpt_off;
@@ -154,6 +193,15 @@ __global__ __launch_bounds__(NW * 64) void k_resident(
         pk[k] = static_cast<uint32_t>(own) | (x > 0 ? 1u << 16 : 0u) | (x < L.nx - 1 ? 1u << 17 : 0u) |
                 (y > 0 ? 1u << 18 : 0u) | (y < L.ny - 1 ? 1u << 19 : 0u) | (z > 0 ? 1u << 20 : 0u) |
                 (z < L.nz - 1 ? 1u << 21 : 0u) | 0x80000000u;
+        if (noise_wave) {
+            // the thermal field of the first step
+            const V3 h = thermal_field(L, seed[k], static_cast<uint32_t>(c), n0);
+            float* t = T + (n0 & 1) * 3 * G.ncells + own;
+            t[0] = h.x;
+            t[1] = h.y;
+            t[2] = h.z;
+            continue;
+        }
         u[k] = load_axis(L, axes, c);
         const float* src = min_ + I.state_off;
         A[own] = src[c];
@@ -177,7 +225,7 @@ __global__ __launch_bounds__(NW * 64) void k_resident(
     // registers (a per-thread pointer would be a vector load every step)
     LevelDev Lf{};
     int f_chunk0 = 0, f_nchunks = 0;
-    double f_ncell = 0.0;
+    double f_inv_ncell = 0.0;
     double H0 = 0.0, H1 = 0.0, H2 = 0.0;   // applied field (Oe) at steps n - 1, n, n + 1 of step n
     double* f_rec = records;
     int f_inst = 0;
@@ -188,7 +236,7 @@ __global__ __launch_bounds__(NW * 64) void k_resident(
         f_inst = S.inst;
         f_chunk0 = S.chunk0;
         f_nchunks = S.nchunks;
-        f_ncell = static_cast<double>(Lf.ncell);
+        f_inv_ncell = 1.0 / static_cast<double>(Lf.ncell);
         f_rec = records + I.rec_off;
         H1 = Lf.hz_oe * wave_at(Lf, n0);
         const double w = wave_at(Lf, n0 + 1);
@@ -196,6 +244,15 @@ __global__ __launch_bounds__(NW * 64) void k_resident(
         s_hz[4 * fs + ((n0 + 1) & 3)] = static_cast<float>(Lf.hz_amp * w);
         acc[fs] = accs[S.inst];
     }
+    // the folding thread's accumulators: in registers when the workgroup has
+    // at most 512 threads, else in LDS
+    constexpr bool kAccReg = CPW == 1 && kResThreads<NW> <= 512;
+    AccDev a_reg{};
+    if (kAccReg && folder) a_reg = acc[fs];
+    AccDev& a = [&]() -> AccDev& {
+        if constexpr (kAccReg) return a_reg;
+        else return acc[fs];
+    }();
     // The folding thread splits its work over the two phases of step n:
     // while the other waves predict, the loop ordinate of step n (from the
     // chunk sums of step n - 1, in a fixed order) and the applied field of
@@ -207,7 +264,7 @@ __global__ __launch_bounds__(NW * 64) void k_resident(
         const float* p = part + (m & 1) * pstride + f_chunk0;
         double sum = 0.0;
         for (int j = 0; j < f_nchunks; ++j) sum += static_cast<double>(p[j]);
-        m_fold = sum / f_ncell;
+        m_fold = sum * f_inv_ncell;
     };
     auto field_ahead = [&](int64_t n) {
         const double w = wave_at(Lf, n + 2);
@@ -235,24 +292,42 @@ __global__ __launch_bounds__(NW * 64) void k_resident(
             if (st > 0) ordinate(n - 1);
             field_ahead(n);
         }
+        // ---- noise waves: the thermal field of step n + 1 (the buffer of
+        //      that parity was last read by the predictor of step n - 1)
+        if (noise_wave && st + 1 < nsteps) {
+#pragma unroll
+            for (int k = 0; k < CPW; ++k) {
+                if (!has[k] || !(pk[k] & 0x80000000u)) continue;
+                const V3 h = thermal_field(*Lk[k], seed[k], static_cast<uint32_t>(cell[k]), n + 1);
+                float* t = T + ((n + 1) & 1) * 3 * G.ncells + static_cast<int>(pk[k] & 0xFFFFu);
+                t[0] = h.x;
+                t[1] = h.y;
+                t[2] = h.z;
+            }
+        }
         // ---- predictor: A -> B
 #pragma unroll
         for (int k = 0; k < CPW; ++k) {
             q[k] = hth[k] = V3{0.0f, 0.0f, 0.0f};
-            if (!has[k] || !(pk[k] & 0x80000000u)) continue;
-            const LevelDev& L = *Lk[k];
+            if (noise_wave || !has[k] || !(pk[k] & 0x80000000u)) continue;
             const int own = static_cast<int>(pk[k] & 0xFFFFu);
             const V3 m = v3(A[own], A[own + 1], A[own + 2]);
             if (ck_now) {
-                float* cp = ckpt + ck_off[k] + ck_idx * 3 * L.ncell;
+                const int N = Lk[k]->ncell;
+                float* cp = ckpt + ck_off[k] + ck_idx * 3 * N;
                 cp[cell[k]] = m.x;
-                cp[L.ncell + cell[k]] = m.y;
-                cp[2 * L.ncell + cell[k]] = m.z;
+                cp[N + cell[k]] = m.y;
+                cp[2 * N + cell[k]] = m.z;
             }
-            const V3 ex = stencil(A, pk[k], 3 * L.nx, 3 * L.nx * L.ny, m);
-            hth[k] = thermal_field(L, seed[k], static_cast<uint32_t>(cell[k]), n);
+            const V3 ex = stencil(A, pk[k], sy[k], sz[k], m);
+            if (NP) {
+                const float* t = T + (n & 1) * 3 * G.ncells + own;
+                hth[k] = v3(t[0], t[1], t[2]);
+            } else {
+                hth[k] = thermal_field(*Lk[k], seed[k], static_cast<uint32_t>(cell[k]), n);
+            }
             V3 mp;
-            heun_predict(L, m, ex, L.has_axes ? u[k] : V3{L.ux, L.uy, L.uz}, hz[k], hth[k], mp, q[k]);
+            heun_predict(Lc[k], m, ex, u[k], hz[k], hth[k], mp, q[k]);
             B[own] = mp.x;
             B[own + 1] = mp.y;
             B[own + 2] = mp.z;
@@ -260,7 +335,7 @@ __global__ __launch_bounds__(NW * 64) void k_resident(
         __syncthreads();
         // ---- loop update of the previous step
         if (folder) {
-            if (st > 0) loop_accumulate_h(acc[fs], Lf, H0, H1, m_fold, f_rec);
+            if (st > 0) loop_accumulate_h(a, Lf, H0, H1, m_fold, f_rec);
             H0 = H1;
             H1 = H2;
             H2 = H3;
@@ -268,16 +343,14 @@ __global__ __launch_bounds__(NW * 64) void k_resident(
         // ---- corrector: B -> A, wave sums of m_z per chunk
 #pragma unroll
         for (int k = 0; k < CPW; ++k) {
-            if (!has[k]) continue;
-            const LevelDev& L = *Lk[k];
+            if (noise_wave || !has[k]) continue;
             const float hz1 = s_hz[4 * slot[k] + ((n + 1) & 3)];
             float mz = 0.0f;
             if (pk[k] & 0x80000000u) {
                 const int own = static_cast<int>(pk[k] & 0xFFFFu);
                 const V3 mp = v3(B[own], B[own + 1], B[own + 2]);
-                const V3 ex = stencil(B, pk[k], 3 * L.nx, 3 * L.nx * L.ny, mp);
-                const V3 mn = heun_correct(L, mp, ex, L.has_axes ? u[k] : V3{L.ux, L.uy, L.uz}, hz1, hth[k],
-                                           q[k]);
+                const V3 ex = stencil(B, pk[k], sy[k], sz[k], mp);
+                const V3 mn = heun_correct(Lc[k], mp, ex, u[k], hz1, hth[k], q[k]);
                 A[own] = mn.x;
                 A[own + 1] = mn.y;
                 A[own + 2] = mn.z;
@@ -296,14 +369,14 @@ __global__ __launch_bounds__(NW * 64) void k_resident(
     }
     if (folder && nsteps > 0) {
         ordinate(n0 + nsteps - 1);
-        loop_accumulate_h(acc[fs], Lf, H0, H1, m_fold, f_rec);
+        loop_accumulate_h(a, Lf, H0, H1, m_fold, f_rec);
     }
     __syncthreads();
     // write back state (buffer (n0 + nsteps) & 1) and accumulators
     float* mout = ((n0 + nsteps) & 1) ? buf1 : buf0;
 #pragma unroll
     for (int k = 0; k < CPW; ++k) {
-        if (!has[k] || !(pk[k] & 0x80000000u)) continue;
+        if (noise_wave || !has[k] || !(pk[k] & 0x80000000u)) continue;
         const int j = wave + k * NW;
         const ChunkDev ch = chunks[G.chunk0 + j];
         const int N = Lk[k]->ncell;
@@ -314,7 +387,6 @@ __global__ __launch_bounds__(NW * 64) void k_resident(
         d[2 * N + cell[k]] = A[own + 2];
     }
     if (folder) {
-        const AccDev a = acc[fs];
         accs[f_inst] = a;
         if (!isfinite(a.m_prev)) atomicOr(status, 1);
     }
