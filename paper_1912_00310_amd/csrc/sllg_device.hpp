@@ -34,6 +34,16 @@ struct U4 {
     uint32_t a, b, c, d;
 };
 
+// A copy of a wave-uniform value in a vector register: the compiler cannot
+// re-read it from memory inside a loop (a scalar reload waits on the same
+// counter as the LDS reads of the step).
+__device__ __forceinline__ float vreg(float x)
+{
+    float r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 // Three-input exclusive or in one gfx950 VALU instruction (truth table 0x96).
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
 {

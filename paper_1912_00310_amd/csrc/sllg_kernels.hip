@@ -91,16 +91,6 @@ __device__ __forceinline__ V3 load_axis(const LevelDev& L, const float* __restri
 // a countdown, so a step has no global loads, no FP64 and no integer
 // division on the critical path of the waves that own cells.
 // ---------------------------------------------------------------------------
-// A copy of a wave-uniform value in a vector register: the compiler cannot
-// re-read it from memory inside a loop (a scalar reload waits on the same
-// counter as the LDS reads of the step).
-__device__ __forceinline__ float vreg(float x)
-{
-    float r;
-    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"(x));
-    return r;
-}
-
 // With NW <= 8 the workgroup has NW more waves: wave NW + w draws the
 // thermal field of step n + 1 for the cells of wave w into an LDS buffer
 // (two step parities) while the cell waves predict step n, so Philox and
