@@ -62,10 +62,16 @@ __global__ __launch_bounds__(NT) void k_adjoint(const InstDev* __restrict__ inst
                                                 float* __restrict__ tape, const double* __restrict__ w,
                                                 double* __restrict__ grads)
 {
-    __shared__ float A[3][NT];       // m_n
-    __shared__ float B[3][NT];       // m'
+    // m_n and m' by step parity: the replay uses parity 0; the reverse walk
+    // writes the tape of step n - 1 into the other parity while step n works,
+    // so a reverse step needs two barriers
+    __shared__ float AA[2][3][NT];
+    __shared__ float BB[2][3][NT];
     __shared__ float HB[2][2][3][NT];   // H'-bar, H-bar per loss
     __shared__ double red[NT / 64][10];
+    // per segment: the applied field of steps nA .. nB and the loss weights
+    // of steps nA .. nB divided by N (FP32, dynamic, ckpt_every + 1 of each)
+    extern __shared__ float seg_tab[];
 
     const int inst = inst0 + static_cast<int>(blockIdx.x);
     const InstDev I = insts[inst];
@@ -77,6 +83,22 @@ __global__ __launch_bounds__(NT) void k_adjoint(const InstDev* __restrict__ inst
     const int64_t K = ckpt_every;
     const int64_t nseg = (NS + K - 1) / K;
     float* tp = tape + static_cast<int64_t>(blockIdx.x) * K * 9 * N;
+
+    float* s_w0 = seg_tab;                   // weights of loss 0 over N
+    float* s_w1 = seg_tab + (K + 1);         // weights of loss 1 over N
+    float* s_hz = seg_tab + 2 * (K + 1);
+    // step constants in vector registers (a scalar reload inside the step
+    // loops would wait on the same counter as the LDS reads)
+    const float c_ex = vreg(L.c_ex), hk = vreg(L.hk), g1 = vreg(L.g1), ag1 = vreg(L.ag1);
+    const float dt = vreg(L.dt), half_dt = vreg(L.half_dt), sigma = vreg(L.sigma);
+    const float inv_g1 = vreg(1.0f / L.g1);
+    LevelDev Lc{};
+    Lc.c_ex = c_ex;
+    Lc.hk = hk;
+    Lc.g1 = g1;
+    Lc.ag1 = ag1;
+    Lc.dt = dt;
+    Lc.half_dt = half_dt;
 
     int ixm = i, ixp = i, iym = i, iyp = i, izm = i, izp = i;
     V3 u = V3{L.ux, L.uy, L.uz};
@@ -110,7 +132,16 @@ __global__ __launch_bounds__(NT) void k_adjoint(const InstDev* __restrict__ inst
 
     for (int64_t seg = nseg - 1; seg >= 0; --seg) {
         const int64_t nA = seg * K, nB = min(nA + K, NS);
+        // ---- the segment's applied fields and loss weights, in parallel
+        __syncthreads();
+        for (int k = i; k <= nB - nA; k += NT) {
+            s_hz[k] = static_cast<float>(L.hz_amp * wave_at(L, nA + k));
+            s_w0[k] = static_cast<float>(w[nA + k] / N);
+            s_w1[k] = static_cast<float>(w[(NS + 1) + nA + k] / N);
+        }
         // ---- forward replay of the segment from its checkpoint
+        float (*A)[NT] = AA[0];
+        float (*B)[NT] = BB[0];
         V3 m = V3{0, 0, 0};
         if (on) {
             const float* c = ckpt + I.ckpt_off + seg * 3 * static_cast<int64_t>(N);
@@ -122,11 +153,11 @@ __global__ __launch_bounds__(NT) void k_adjoint(const InstDev* __restrict__ inst
             float* t = tp + (n - nA) * 9 * N;
             V3 q, hth, mp;
             if (on) {
-                const float hz0 = static_cast<float>(L.hz_amp * wave_at(L, n));
+                const float hz0 = s_hz[n - nA];
                 const V3 xi = gauss3(philox_cell(I.seed, static_cast<uint32_t>(L.level_tag), kTagNoise,
                                                  static_cast<uint32_t>(i), static_cast<uint64_t>(n)));
-                hth = V3{L.sigma * xi.x, L.sigma * xi.y, L.sigma * xi.z};
-                heun_predict(L, m, nb(A, m), u, hz0, hth, mp, q);
+                hth = V3{sigma * xi.x, sigma * xi.y, sigma * xi.z};
+                heun_predict(Lc, m, nb(A, m), u, hz0, hth, mp, q);
                 put(B, mp);
                 t[i] = m.x;
                 t[N + i] = m.y;
@@ -140,43 +171,52 @@ __global__ __launch_bounds__(NT) void k_adjoint(const InstDev* __restrict__ inst
             }
             __syncthreads();
             if (on) {
-                const float hz1 = static_cast<float>(L.hz_amp * wave_at(L, n + 1));
-                m = heun_correct(L, mp, nb(B, mp), u, hz1, hth, q);
+                const float hz1 = s_hz[n + 1 - nA];
+                m = heun_correct(Lc, mp, nb(B, mp), u, hz1, hth, q);
                 put(A, m);
             }
             __syncthreads();
         }
+        // the tape of the segment's last step in LDS and registers, the step
+        // before it in registers: each reverse step puts the tape of the step
+        // before it into the other parity and loads the one before that
+        auto load_tape = [&](int64_t n, V3& a, V3& b, V3& c) {
+            const float* t = tp + (n - nA) * 9 * N;
+            a = V3{t[i], t[N + i], t[2 * N + i]};
+            b = V3{t[3 * N + i], t[4 * N + i], t[5 * N + i]};
+            c = V3{t[6 * N + i], t[7 * N + i], t[8 * N + i]};
+        };
+        V3 cm = V3{0, 0, 0}, cp = V3{0, 0, 0}, cx = V3{0, 0, 0};   // step n
+        V3 tm = V3{0, 0, 0}, tp_ = V3{0, 0, 0}, tx = V3{0, 0, 0};  // step n - 1
+        if (on) {
+            load_tape(nB - 1, cm, cp, cx);
+            put(AA[(nB - 1) & 1], cm);
+            put(BB[(nB - 1) & 1], cp);
+            if (nB - 1 > nA) load_tape(nB - 2, tm, tp_, tx);
+        }
+        __syncthreads();
         // ---- reverse walk of the segment
         for (int64_t n = nB - 1; n >= nA; --n) {
-            const float* t = tp + (n - nA) * 9 * N;
-            V3 mm = V3{0, 0, 0}, mp = V3{0, 0, 0}, xi = V3{0, 0, 0};
-            if (on) {
-                mm = V3{t[i], t[N + i], t[2 * N + i]};
-                mp = V3{t[3 * N + i], t[4 * N + i], t[5 * N + i]};
-                xi = V3{t[6 * N + i], t[7 * N + i], t[8 * N + i]};
-                put(A, mm);
-                put(B, mp);
-            }
-            __syncthreads();
+            const V3 mm = cm, mp = cp, xi = cx;
+            float (*A)[NT] = AA[n & 1];
+            float (*B)[NT] = BB[n & 1];
             V3 ex, exq, H, f, Hp, fp, mn, mpb[2], mb[2], fb[2];
             float ip = 0.f, iq = 0.f;
             if (on) {
-                const float hz0 = static_cast<float>(L.hz_amp * wave_at(L, n));
-                const float hz1 = static_cast<float>(L.hz_amp * wave_at(L, n + 1));
-                const V3 hth = V3{L.sigma * xi.x, L.sigma * xi.y, L.sigma * xi.z};
+                const float hz0 = s_hz[n - nA];
+                const float hz1 = s_hz[n + 1 - nA];
+                const V3 hth = V3{sigma * xi.x, sigma * xi.y, sigma * xi.z};
                 ex = nb(A, mm);
-                H = eff_field(L.c_ex, L.hk, mm, ex, u, hz0, hth);
-                f = llg_rhs(L.g1, L.ag1, mm, H);
-                const V3 pv = V3{fmaf(L.dt, f.x, mm.x), fmaf(L.dt, f.y, mm.y), fmaf(L.dt, f.z, mm.z)};
+                H = eff_field(c_ex, hk, mm, ex, u, hz0, hth);
+                f = llg_rhs(g1, ag1, mm, H);
+                const V3 pv = V3{fmaf(dt, f.x, mm.x), fmaf(dt, f.y, mm.y), fmaf(dt, f.z, mm.z)};
                 ip = __builtin_amdgcn_rsqf(dot3(pv, pv));
                 exq = nb(B, mp);
-                Hp = eff_field(L.c_ex, L.hk, mp, exq, u, hz1, hth);
-                fp = llg_rhs(L.g1, L.ag1, mp, Hp);
+                Hp = eff_field(c_ex, hk, mp, exq, u, hz1, hth);
+                fp = llg_rhs(g1, ag1, mp, Hp);
                 // q as the forward step forms it: (m + dt/2 f) + dt/2 f'
-                const V3 q0 = V3{fmaf(L.half_dt, f.x, mm.x), fmaf(L.half_dt, f.y, mm.y),
-                                 fmaf(L.half_dt, f.z, mm.z)};
-                const V3 qv = V3{fmaf(L.half_dt, fp.x, q0.x), fmaf(L.half_dt, fp.y, q0.y),
-                                 fmaf(L.half_dt, fp.z, q0.z)};
+                const V3 q0 = V3{fmaf(half_dt, f.x, mm.x), fmaf(half_dt, f.y, mm.y), fmaf(half_dt, f.z, mm.z)};
+                const V3 qv = V3{fmaf(half_dt, fp.x, q0.x), fmaf(half_dt, fp.y, q0.y), fmaf(half_dt, fp.z, q0.z)};
                 iq = __builtin_amdgcn_rsqf(dot3(qv, qv));
                 mn = scale3(iq, qv);
                 const V3 mxH = cross3(mp, Hp);
@@ -185,15 +225,23 @@ __global__ __launch_bounds__(NT) void k_adjoint(const InstDev* __restrict__ inst
                 for (int l = 0; l < 2; ++l) {
                     const V3 qb = unit_T(mn, iq, lam[l]);
                     mb[l] = qb;
-                    const V3 fpb = scale3(L.half_dt, qb);
+                    const V3 fpb = scale3(half_dt, qb);
                     fb[l] = fpb;
-                    const V3 hpb = rhs_dH_T(L.g1, L.ag1, mp, fpb);
-                    mpb[l] = rhs_dm_T(L.g1, L.ag1, mp, Hp, fpb);
-                    g[l][2] += static_cast<double>(dot3(fpb, fp) / L.g1);
-                    g[l][3] += static_cast<double>(-L.g1 * dot3(fpb, dmp));
+                    const V3 hpb = rhs_dH_T(g1, ag1, mp, fpb);
+                    mpb[l] = rhs_dm_T(g1, ag1, mp, Hp, fpb);
+                    g[l][2] += static_cast<double>(dot3(fpb, fp) * inv_g1);
+                    g[l][3] += static_cast<double>(-g1 * dot3(fpb, dmp));
                     HB[l][0][0][i] = hpb.x;
                     HB[l][0][1][i] = hpb.y;
                     HB[l][0][2][i] = hpb.z;
+                }
+                if (n > nA) {
+                    put(AA[(n - 1) & 1], tm);
+                    put(BB[(n - 1) & 1], tp_);
+                    cm = tm;
+                    cp = tp_;
+                    cx = tx;
+                    if (n - 1 > nA) load_tape(n - 2, tm, tp_, tx);
                 }
             }
             __syncthreads();
@@ -207,19 +255,19 @@ __global__ __launch_bounds__(NT) void k_adjoint(const InstDev* __restrict__ inst
                     const V3 d = nb(S, hpb);
                     const float uh = dot3(u, hpb);
                     V3 v = mpb[l];
-                    v.x = fmaf(L.c_ex, d.x, fmaf(L.hk * uh, u.x, v.x));
-                    v.y = fmaf(L.c_ex, d.y, fmaf(L.hk * uh, u.y, v.y));
-                    v.z = fmaf(L.c_ex, d.z, fmaf(L.hk * uh, u.z, v.z));
+                    v.x = fmaf(c_ex, d.x, fmaf(hk * uh, u.x, v.x));
+                    v.y = fmaf(c_ex, d.y, fmaf(hk * uh, u.y, v.y));
+                    v.z = fmaf(c_ex, d.z, fmaf(hk * uh, u.z, v.z));
                     g[l][0] += static_cast<double>(dot3(hpb, exq));
                     g[l][1] += static_cast<double>(dot3(mp, u) * uh);
                     g[l][4] += static_cast<double>(dot3(hpb, xi));
                     const V3 pb = unit_T(mp, ip, v);
                     mb[l] = add3(mb[l], pb);
-                    fb[l] = V3{fmaf(L.dt, pb.x, fb[l].x), fmaf(L.dt, pb.y, fb[l].y), fmaf(L.dt, pb.z, fb[l].z)};
-                    const V3 hb = rhs_dH_T(L.g1, L.ag1, mm, fb[l]);
-                    mb[l] = add3(mb[l], rhs_dm_T(L.g1, L.ag1, mm, H, fb[l]));
-                    g[l][2] += static_cast<double>(dot3(fb[l], f) / L.g1);
-                    g[l][3] += static_cast<double>(-L.g1 * dot3(fb[l], dm));
+                    fb[l] = V3{fmaf(dt, pb.x, fb[l].x), fmaf(dt, pb.y, fb[l].y), fmaf(dt, pb.z, fb[l].z)};
+                    const V3 hb = rhs_dH_T(g1, ag1, mm, fb[l]);
+                    mb[l] = add3(mb[l], rhs_dm_T(g1, ag1, mm, H, fb[l]));
+                    g[l][2] += static_cast<double>(dot3(fb[l], f) * inv_g1);
+                    g[l][3] += static_cast<double>(-g1 * dot3(fb[l], dm));
                     HB[l][1][0][i] = hb.x;
                     HB[l][1][1][i] = hb.y;
                     HB[l][1][2][i] = hb.z;
@@ -234,20 +282,20 @@ __global__ __launch_bounds__(NT) void k_adjoint(const InstDev* __restrict__ inst
                     const V3 d = nb(S, hb);
                     const float uh = dot3(u, hb);
                     V3 v = mb[l];
-                    v.x = fmaf(L.c_ex, d.x, fmaf(L.hk * uh, u.x, v.x));
-                    v.y = fmaf(L.c_ex, d.y, fmaf(L.hk * uh, u.y, v.y));
-                    v.z = fmaf(L.c_ex, d.z, fmaf(L.hk * uh, u.z, v.z));
+                    v.x = fmaf(c_ex, d.x, fmaf(hk * uh, u.x, v.x));
+                    v.y = fmaf(c_ex, d.y, fmaf(hk * uh, u.y, v.y));
+                    v.z = fmaf(c_ex, d.z, fmaf(hk * uh, u.z, v.z));
                     g[l][0] += static_cast<double>(dot3(hb, ex));
                     g[l][1] += static_cast<double>(dot3(mm, u) * uh);
                     g[l][4] += static_cast<double>(dot3(hb, xi));
-                    v.z += static_cast<float>(w[l * (NS + 1) + n] / N);
+                    v.z += (l == 0 ? s_w0 : s_w1)[n - nA];
                     lam[l] = v;
                 }
             }
-            // the next step rewrites A, B and the first H-bar buffers only after
-            // its own first barrier; everything read above is in registers or
-            // in the second H-bar buffers
-            __syncthreads();
+            // no barrier: the next step reads m_n, m' of the other parity
+            // (written before this step's first barrier), writes the first
+            // H-bar buffers (last read before this step's second barrier) and
+            // writes the second ones only after its own first barrier
         }
     }
     // ---- FP64 block reduction in fixed order
