@@ -54,8 +54,14 @@ __device__ __forceinline__ V3 rhs_dm_T(float g1, float ag1, V3 m, V3 H, V3 v)
               -g1 * t1.z - ag1 * (t2.z + t3.z)};
 }
 
+// Workgroups of up to 256 cells get NT more threads: thread NT + i draws the
+// thermal field of cell i for the next replay step into LDS while the cell
+// threads step the current one.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_adjoint(const InstDev* __restrict__ insts, int inst0,
+constexpr int kAdjThreads = NT <= 256 ? 2 * NT : NT;
+
+template <int NT>
+__global__ __launch_bounds__(kAdjThreads<NT>) void k_adjoint(const InstDev* __restrict__ insts, int inst0,
                                                 const LevelDev* __restrict__ levels,
                                                 const float* __restrict__ axes,
                                                 const float* __restrict__ ckpt, int ckpt_every,
@@ -69,6 +75,7 @@ __global__ __launch_bounds__(NT) void k_adjoint(const InstDev* __restrict__ inst
     __shared__ float BB[2][3][NT];
     __shared__ float HB[2][2][3][NT];   // H'-bar, H-bar per loss
     __shared__ double red[NT / 64][10];
+    __shared__ float XI[2][3][NT];      // replay noise by step parity (noise threads)
     // per segment: the applied field of steps nA .. nB and the loss weights
     // of steps nA .. nB divided by N (FP32, dynamic, ckpt_every + 1 of each)
     extern __shared__ float seg_tab[];
@@ -77,8 +84,18 @@ __global__ __launch_bounds__(NT) void k_adjoint(const InstDev* __restrict__ inst
     const InstDev I = insts[inst];
     const LevelDev& L = levels[I.level];
     const int N = L.ncell, nx = L.nx, ny = L.ny, nz = L.nz;
-    const int i = threadIdx.x;
-    const bool on = i < N;
+    constexpr bool NP = kAdjThreads<NT> > NT;
+    const bool noise_thread = NP && static_cast<int>(threadIdx.x) >= NT;
+    const int i = noise_thread ? static_cast<int>(threadIdx.x) - NT : static_cast<int>(threadIdx.x);
+    const bool on = i < N && !noise_thread;
+    const bool draws = noise_thread && i < N;
+    auto draw = [&](int64_t n) {
+        const V3 xi = gauss3(philox_cell(I.seed, static_cast<uint32_t>(L.level_tag), kTagNoise,
+                                         static_cast<uint32_t>(i), static_cast<uint64_t>(n)));
+        XI[n & 1][0][i] = xi.x;
+        XI[n & 1][1][i] = xi.y;
+        XI[n & 1][2][i] = xi.z;
+    };
     const int64_t NS = L.n_steps;
     const int64_t K = ckpt_every;
     const int64_t nseg = (NS + K - 1) / K;
@@ -148,14 +165,23 @@ __global__ __launch_bounds__(NT) void k_adjoint(const InstDev* __restrict__ inst
             m = V3{c[i], c[N + i], c[2 * N + i]};
             put(A, m);
         }
+        if (draws) draw(nA);
         __syncthreads();
         for (int64_t n = nA; n < nB; ++n) {
             float* t = tp + (n - nA) * 9 * N;
             V3 q, hth, mp;
+            // the noise of step n + 1 (its buffer was last read before the
+            // previous step's second barrier)
+            if (draws && n + 1 < nB) draw(n + 1);
             if (on) {
                 const float hz0 = s_hz[n - nA];
-                const V3 xi = gauss3(philox_cell(I.seed, static_cast<uint32_t>(L.level_tag), kTagNoise,
-                                                 static_cast<uint32_t>(i), static_cast<uint64_t>(n)));
+                V3 xi;
+                if (NP) {
+                    xi = V3{XI[n & 1][0][i], XI[n & 1][1][i], XI[n & 1][2][i]};
+                } else {
+                    xi = gauss3(philox_cell(I.seed, static_cast<uint32_t>(L.level_tag), kTagNoise,
+                                            static_cast<uint32_t>(i), static_cast<uint64_t>(n)));
+                }
                 hth = V3{sigma * xi.x, sigma * xi.y, sigma * xi.z};
                 heun_predict(Lc, m, nb(A, m), u, hz0, hth, mp, q);
                 put(B, mp);
@@ -298,15 +324,17 @@ __global__ __launch_bounds__(NT) void k_adjoint(const InstDev* __restrict__ inst
             // writes the second ones only after its own first barrier
         }
     }
-    // ---- FP64 block reduction in fixed order
+    // ---- FP64 block reduction in fixed order (cell threads)
     const int lane = i & 63, wv = i >> 6;
-    for (int l = 0; l < 2; ++l)
-        for (int k = 0; k < 5; ++k) {
-            const double s = wave_sum_d(g[l][k]);
-            if (lane == 0) red[wv][l * 5 + k] = s;
-        }
+    if (!noise_thread) {
+        for (int l = 0; l < 2; ++l)
+            for (int k = 0; k < 5; ++k) {
+                const double s = wave_sum_d(g[l][k]);
+                if (lane == 0) red[wv][l * 5 + k] = s;
+            }
+    }
     __syncthreads();
-    if (i < 10) {
+    if (!noise_thread && i < 10) {
         double s = 0.0;
         for (int k = 0; k < NT / 64; ++k) s += red[k][i];
         grads[static_cast<int64_t>(inst) * 10 + i] = s;

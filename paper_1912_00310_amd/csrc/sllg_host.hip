@@ -2010,16 +2010,17 @@ int sllg_grad(sllg_ctx* C, int32_t level, double g_area[4], double g_hc[4])
                  : h.ncell <= 512 ? 512 : 1024;
     // dynamic LDS: the segment's loss weights and applied field (three FP32
     // per step); static LDS: m_n and m' of two parities, four H-bar planes,
-    // sums
+    // replay noise of two parities, sums
     const size_t seg_lds = 12 * (size_t)(C->ckpt_every + 1);
-    const size_t static_lds = (size_t)nt * (2 * 2 * 3 * 4 + 2 * 2 * 3 * 4) + (size_t)(nt / 64) * 10 * 8;
+    const size_t static_lds = (size_t)nt * (2 * 2 * 3 * 4 + 2 * 2 * 3 * 4 + 2 * 3 * 4) + (size_t)(nt / 64) * 10 * 8;
     if (seg_lds + static_lds > (size_t)C->max_lds)
         return fail(SLLG_E_INVAL, "ckpt_every %d too large for the adjoint's LDS (at most %d)", C->ckpt_every,
                     (int)((C->max_lds - static_lds) / 12) - 1);
 #define SLLG_ADJ(NT)                                                                                          \
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adjoint<NT>),                                  \
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)seg_lds);                      \
-    hipLaunchKernelGGL(k_adjoint<NT>, dim3((unsigned)R), dim3(NT), seg_lds, C->stream, C->d_insts, h.inst0,   \
+    hipLaunchKernelGGL(k_adjoint<NT>, dim3((unsigned)R), dim3(kAdjThreads<NT>), seg_lds, C->stream,          \
+                       C->d_insts, h.inst0,                                                                   \
                        C->d_levels, C->d_axes, C->d_ckpt, C->ckpt_every, C->d_tape, C->d_weights, C->d_grads)
     switch (nt) {
     case 64: SLLG_ADJ(64); break;
