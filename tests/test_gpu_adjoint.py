@@ -66,6 +66,19 @@ def test_short_sweep_area_gradient(P, orc):
     assert ok, (ga, ra, r)
 
 
+@pytest.mark.parametrize("dims", [(2, 4, 7), (4, 8, 12)])
+def test_area_gradient_other_workgroup_sizes(P, orc, dims):
+    # 56 cells (64 threads + noise threads) and 384 cells (512 threads, the
+    # replay draws its noise inline)
+    wl = W.workload("rod_b4_adjoint64")
+    wl["material"]["sweep_Oe_per_ns"] *= 40        # 1000 steps
+    wl["levels"][0].update(nx=dims[0], ny=dims[1], nz=dims[2], n_real=2)
+    ga, gh, st = gpu_grads(P, wl, ckpt=256)
+    ra, rh, so = oracle_grads(orc, wl)
+    ok, r = rel_close(ga, ra, 1e-3)
+    assert ok, (ga, ra, r)
+
+
 def test_checkpoint_interval_does_not_change_gradient(P):
     wl = W.workload("rod_b4_adjoint64")
     wl["material"]["sweep_Oe_per_ns"] *= 20

@@ -157,6 +157,26 @@ def test_resident_small_grids(P, orc):
         _trajectory_check(P, orc, wl, 200, plan=P.PLAN_RESIDENT, every=50)
 
 
+# resident workgroups of every width: 2 chunks (4 cell waves + noise waves),
+# 6 chunks (8 + noise waves), 16 chunks (16 waves, the folder owns a chunk,
+# noise drawn inline), 18 chunks (two chunks per wave)
+@pytest.mark.parametrize("dims", [(4, 4, 8), (6, 8, 8), (10, 10, 10), (8, 12, 12)])
+def test_resident_workgroup_widths(P, orc, dims):
+    wl = W.workload("block_b2_cone10")
+    wl["levels"][0].update(nx=dims[0], ny=dims[1], nz=dims[2], n_real=2)
+    wl["material"]["sweep_Oe_per_ns"] = 1e5
+    _trajectory_check(P, orc, wl, 120, plan=P.PLAN_RESIDENT, every=40)
+    out = []
+    for plan in (P.PLAN_RESIDENT, P.PLAN_STREAM):
+        sim = P.Sim(wl["material"], wl["levels"])
+        sim.set_plan(0, plan)
+        sim.run_steps(120)
+        out.append((sim.get_state(0, 1), sim.loop(0, 1)[1], sim.kernel_name(0)))
+        sim.close()
+    assert np.array_equal(out[0][0], out[1][0]), out[0][2]
+    assert np.abs(out[0][1] - out[1][1]).max() < 1e-6
+
+
 def test_realizations_are_independent_streams(P, orc):
     wl = W.workload("rod_b4_single")
     wl["levels"][0]["n_real"] = 3
