@@ -6,7 +6,7 @@ gfx950 kernels of ``libsllg.so`` behind the C ABI of ``include/sllg.h``;
 ``sllg`` is its Python binding.
 """
 from .sllg import (PLAN_AUTO, PLAN_RESIDENT, PLAN_SLAB, PLAN_STREAM, Sim,  # noqa: F401
-                   SllgError, lib, philox_probe)
+                   SllgError, lib, loop_area_hc, philox_probe)
 
-__all__ = ["Sim", "SllgError", "lib", "philox_probe", "PLAN_AUTO", "PLAN_RESIDENT", "PLAN_STREAM",
-           "PLAN_SLAB"]
+__all__ = ["Sim", "SllgError", "lib", "loop_area_hc", "philox_probe", "PLAN_AUTO", "PLAN_RESIDENT",
+           "PLAN_STREAM", "PLAN_SLAB"]

@@ -302,3 +302,66 @@ def philox_probe(seed, level, tag, cells, steps, device="cuda:0"):
         raw.ctypes.data_as(C.POINTER(C.c_uint32)), nrm.ctypes.data_as(C.POINTER(C.c_float)),
         C.c_void_p(ptr), C.c_void_p(stream)))
     return raw, nrm
+
+
+# ---------------------------------------------------------------------------
+# torch.autograd interface to sllg_grad
+# ---------------------------------------------------------------------------
+def _loop_function():
+    import torch
+
+    class SllgLoop(torch.autograd.Function):
+        """(S_sim, Hc_sim) of the ensemble-mean loop of one level as a
+        function of its simulated K, A (J/m^3, J/m), its damping alpha and the
+        Ms multiplier ms_scale (0-d float64 tensors).
+
+        The forward runs one sweep of every realization of ``level`` under
+        ``material`` with those four values substituted (K and A are taken as
+        the simulated values, so the coarse-graining rule is not applied to
+        them again; the field and loop scales of the level stay as the rule
+        gives them) and keeps the context; the first backward calls
+        sllg_grad, the discrete adjoint under the same noise, which gives the
+        gradients of both outputs, and frees it.  Hc_sim is NaN
+        when a branch of the mean loop never crosses zero; its gradient is
+        then NaN too.
+        """
+
+        @staticmethod
+        def forward(ctx, K, A, alpha, ms_scale, material, level, ckpt_every=256):
+            mat = dict(material, K0=float(K), A0=float(A), ms_scale=float(ms_scale), scale_AK=False,
+                       sr_ref_Oe_per_ns=0.0)
+            lvd = dict(level, alpha=float(alpha))
+            sim = Sim(mat, [lvd], ckpt_every=ckpt_every)
+            sim.run_sweep()
+            st = sim.loop(0, -1)[2]
+            ctx.sim = sim
+            return (torch.tensor(st["S_sim"], dtype=torch.float64),
+                    torch.tensor(st["Hc_sim"], dtype=torch.float64))
+
+        @staticmethod
+        def backward(ctx, gS, gHc):
+            # one adjoint sweep gives both rows; a second backward (the other
+            # output) reuses them
+            if getattr(ctx, "rows", None) is None:
+                ctx.rows = ctx.sim.grad(0)
+                ctx.sim.close()
+                ctx.sim = None
+            ga, gh = ctx.rows
+            g = gS.double() * torch.tensor(ga, dtype=torch.float64)
+            if float(gHc) != 0.0:
+                g = g + gHc.double() * torch.tensor(gh, dtype=torch.float64)
+            return g[0], g[1], g[2], g[3], None, None, None
+
+    return SllgLoop
+
+
+_SLLG_LOOP = None
+
+
+def loop_area_hc(K, A, alpha, ms_scale, material: dict, level: dict, ckpt_every: int = 256):
+    """(S_sim, Hc_sim) = SllgLoop.apply(K, A, alpha, ms_scale, ...): the
+    differentiable loop of one level (see SllgLoop)."""
+    global _SLLG_LOOP
+    if _SLLG_LOOP is None:
+        _SLLG_LOOP = _loop_function()
+    return _SLLG_LOOP.apply(K, A, alpha, ms_scale, material, level, ckpt_every)
