@@ -6,10 +6,10 @@ invariant with b to 10-15 % (Fig. 2c).  With sllg_grad the level's simulated
 K, A, alpha and ms_scale can instead be fitted so that its loop area and
 coercive field reproduce a target, e.g. the loops of the fine (b = 1) grid.
 
-``fit_level`` runs damped Gauss-Newton steps on the residuals
-(S - S*, w (Hc - Hc*)) in the logarithms of the fitted parameters; every
-step costs one forward sweep of the level and one adjoint sweep, both on the
-GPU through the C ABI.
+``fit_level`` runs Levenberg-Marquardt steps on the residuals
+(S - S*, w (Hc - Hc*)) in the logarithms of the fitted parameters; a trial
+point costs one forward sweep of the level, an accepted one also an adjoint
+sweep, both on the GPU through the C ABI.
 """
 from __future__ import annotations
 
@@ -20,42 +20,125 @@ from .sllg import loop_area_hc
 PARAMS = ("K", "A", "alpha", "ms_scale")
 
 
+def _evaluate(material, level, vals, fit, target, hc_weight, ckpt_every):
+    """Residuals (S - S*, w (Hc - Hc*)) at vals, and a function that returns
+    their Jacobian in the logarithms of the fitted parameters (one adjoint
+    sweep; None where a residual is not finite)."""
+    import torch
+    x = {k: torch.tensor(vals[k], dtype=torch.float64, requires_grad=k in fit) for k in PARAMS}
+    S, Hc = loop_area_hc(x["K"], x["A"], x["alpha"], x["ms_scale"], material, level, ckpt_every)
+    Sv, Hv = float(S.detach()), float(Hc.detach())
+    res, outs, wts = [Sv - target[0]], [S], [1.0]
+    if hc_weight > 0 and math.isfinite(target[1]):
+        # a loop that stops crossing zero counts as missing the target by Hmax
+        res.append(hc_weight * ((Hv if math.isfinite(Hv) else 1e300) - target[1]))
+        outs.append(Hc)
+        wts.append(hc_weight)
+    res = [min(max(r, -1e30), 1e30) for r in res]
+
+    def jacobian():
+        if not all(math.isfinite(r) and abs(r) < 1e29 for r in res):
+            return None
+        rows = []
+        for j, o in enumerate(outs):
+            g = torch.autograd.grad(o, [x[k] for k in fit], retain_graph=j + 1 < len(outs))
+            rows.append([wts[j] * float(gi) * vals[k] for gi, k in zip(g, fit)])
+        return torch.tensor(rows, dtype=torch.float64)
+
+    return res, jacobian, Sv, Hv
+
+
 def fit_level(material: dict, level: dict, start: dict, target, fit=("K",), hc_weight=0.0,
-              steps: int = 6, damping: float = 1e-3, ckpt_every: int = 256, tol: float = 1e-4):
+              steps: int = 8, ckpt_every: int = 256, tol: float = 1e-4, max_log_step: float = 0.25):
     """Fit the parameters named in ``fit`` (a subset of K, A, alpha,
     ms_scale) of one level so that its ensemble-mean loop has area
     target[0] and, when hc_weight > 0, coercive field target[1] (simulation
     units, Oe).  ``start`` holds all four values (K and A simulated, J/m^3
-    and J/m).  Returns (values, history); history lists per step the values,
-    S, Hc and the squared residual norm.
+    and J/m).  Levenberg-Marquardt in the logarithms of the parameters: a
+    step that does not lower the squared residual is undone and the damping
+    raised.  Returns (values, history); history lists the accepted points
+    (values, S, Hc, squared residual).
     """
     import torch
     vals = {k: float(start[k]) for k in PARAMS}
-    hist = []
-    for it in range(steps + 1):
-        x = {k: torch.tensor(vals[k], dtype=torch.float64, requires_grad=k in fit) for k in PARAMS}
-        S, Hc = loop_area_hc(x["K"], x["A"], x["alpha"], x["ms_scale"], material, level, ckpt_every)
-        Sv, Hv = float(S.detach()), float(Hc.detach())
-        res = [Sv - target[0]]
-        outs = [S]
-        if hc_weight > 0 and math.isfinite(Hv) and math.isfinite(target[1]):
-            res.append(hc_weight * (Hv - target[1]))
-            outs.append(Hc)
-        err = sum(r * r for r in res)
-        hist.append(dict(vals, S=Sv, Hc=Hv, err=err))
-        if it == steps or err <= (tol * abs(target[0])) ** 2:
+    res, jac, Sv, Hv = _evaluate(material, level, vals, fit, target, hc_weight, ckpt_every)
+    J = jac()
+    err = sum(r * r for r in res)
+    hist = [dict(vals, S=Sv, Hc=Hv, err=err)]
+    mu = 1e-3
+    for _ in range(steps):
+        if err <= (tol * abs(target[0])) ** 2 or J is None:
             break
-        # Jacobian of the residuals in log-parameters: dr/dlog p = p dr/dp
-        rows = []
-        for j, o in enumerate(outs):
-            g = torch.autograd.grad(o, [x[k] for k in fit], retain_graph=j + 1 < len(outs))
-            w = 1.0 if j == 0 else hc_weight
-            rows.append([w * float(gi) * vals[k] for gi, k in zip(g, fit)])
-        J = torch.tensor(rows, dtype=torch.float64)
         r = torch.tensor(res, dtype=torch.float64)
         JtJ = J.T @ J
-        lam = damping * float(torch.trace(JtJ)) / len(fit) + 1e-300
-        step = torch.linalg.solve(JtJ + lam * torch.eye(len(fit), dtype=torch.float64), -(J.T @ r))
-        for k, dl in zip(fit, step.tolist()):
-            vals[k] *= math.exp(max(-0.5, min(0.5, dl)))   # at most a factor e^0.5 per step
+        dlog = torch.linalg.solve(JtJ + mu * torch.diag(torch.diag(JtJ) + 1e-300), -(J.T @ r))
+        scale = min(1.0, max_log_step / max(1e-300, float(dlog.abs().max())))
+        trial = dict(vals)
+        for k, d in zip(fit, (dlog * scale).tolist()):
+            trial[k] = vals[k] * math.exp(d)
+        res_t, jac_t, S_t, H_t = _evaluate(material, level, trial, fit, target, hc_weight, ckpt_every)
+        err_t = sum(x * x for x in res_t)
+        if err_t < err:
+            vals, res, J, err = trial, res_t, jac_t(), err_t
+            hist.append(dict(vals, S=S_t, Hc=H_t, err=err))
+            mu = max(mu / 3.0, 1e-6)
+        else:
+            mu *= 10.0
     return vals, hist
+
+
+def fit_coarse_to_fine(material: dict, fine: dict, coarse: dict, fit=("K", "A"), steps: int = 8,
+                       log=print):
+    """Run the fine level once, then fit the coarse level's parameters so
+    that its loop reproduces the fine loop's area and coercive field in
+    physical units (H / zeta and the Eq. 13 magnetisation factor of each
+    level).  Returns (fine stats, rule values, fitted values, history)."""
+    from .sllg import Sim
+    sim = Sim(material, [fine])
+    n = int(sim.level_params(0)["n_steps"])
+    done = 0
+    while done < n:   # in pieces, with progress
+        k = min(2_000_000, n - done)
+        sim.run_steps(k)
+        sim.synchronize()
+        done += k
+        log(f"fine grid: {done}/{n} steps")
+    sf = sim.loop(0, -1)[2]
+    sim.close()
+    sim = Sim(material, [coarse])
+    pc = sim.level_params(0)
+    sim.close()
+    hs, cM = pc["hscale"], pc["cM"]
+    target = (sf["S_phys"] * hs / cM, sf["Hc_phys"] * hs)
+    start = dict(K=pc["K"], A=pc["A"], alpha=pc["alpha"], ms_scale=material.get("ms_scale", 1.0))
+    vals, hist = fit_level(material, coarse, start, target, fit=fit, hc_weight=target[0] / target[1],
+                           steps=steps)
+    for h in hist:
+        h["S_phys"] = h["S"] * cM / hs
+        h["Hc_phys"] = h["Hc"] / hs
+    return sf, start, vals, hist
+
+
+if __name__ == "__main__":
+    # The b = 4 rod fitted to the b = 1 rod: Hmax = 500 Oe cosine sweep at
+    # 250 Oe/ns, alpha = 1, easy axes in a 5 degree cone, T = 310 K
+    # (python -m paper_1912_00310_amd.fit from the repository root).
+    import json
+    import sys
+
+    import sllg_workloads as W
+    from .sllg import Sim
+    mat = dict(W.BASE_MATERIAL, Hmax_Oe=500.0, sweep_Oe_per_ns=250.0, wave="cosine")
+    common = dict(seed_base=1, alpha=1.0, cone_deg=5.0, axis_seed=11)
+    fine = dict(common, nx=8, ny=24, nz=56, b=1.0, n_real=8, dt_s=1e-15, record_every=1000)
+    coarse = dict(common, nx=2, ny=6, nz=14, b=4.0, n_real=64, dt_s=5e-15, record_every=1)
+    keys = ("S_phys", "S_se", "Hc_phys", "Hc_se", "Mr_phys")
+    rule = Sim(mat, [coarse])
+    rule.run_sweep()
+    sr = rule.loop(0, -1)[2]
+    rule.close()
+    sf, start, vals, hist = fit_coarse_to_fine(mat, fine, coarse,
+                                               log=lambda s: print(s, file=sys.stderr, flush=True))
+    print(json.dumps({"fine_b1": {k: sf[k] for k in keys}, "coarse_b4_rule": {k: sr[k] for k in keys},
+                      "rule": start, "fitted": vals,
+                      "history": [{k: h[k] for k in ("K", "A", "S_phys", "Hc_phys", "err")} for h in hist]}))
