@@ -142,9 +142,12 @@ int sllg_loop(sllg_ctx* ctx, int32_t level, int32_t real, double* H_Oe, double* 
  * of the ensemble-mean loop area S_sim (g_area) and of the coercive field
  * Hc_sim of the ensemble-mean loop (g_hc) with respect to
  * (K, A, alpha, ms_scale), K and A being the level's simulated values.
- * Needs a completed sweep run with ckpt_every > 0 and record_every == 1.
- * g_hc is NaN when the mean loop has no crossing on a branch.
- * FP64 accumulation; synchronises the stream. */
+ * Needs a completed sweep run with ckpt_every > 0 and record_every == 1,
+ * and a level of at most 1024 cells.  One segment of ckpt_every steps has
+ * its applied field and loss weights in LDS: ckpt_every may be at most 3305
+ * for levels of 513-1024 cells (11000 and more for smaller ones); beyond
+ * that SLLG_E_INVAL.  g_hc is NaN when the mean loop has no crossing on a
+ * branch.  FP64 accumulation; synchronises the stream. */
 int sllg_grad(sllg_ctx* ctx, int32_t level, double g_area[4], double g_hc[4]);
 
 /* Thread-local text of the last error. */
