@@ -308,3 +308,38 @@ def test_rows2_bit_identical_to_window_kernel(P, cone):
     for st, mh in out[1:]:
         assert np.array_equal(st, out[0][0])
         assert np.abs(mh - out[0][1]).max() < 1e-6
+
+
+# ---- full-size workloads in the launch configuration the benchmark times
+def test_block_full_size_bench_configuration(P, orc):
+    # the 128 x 128 x 512 block with k_rows2<1024,2> and 19 planes per tile,
+    # three steps against the FP64 oracle over all 8.4M cells
+    wl = W.workload("block_b2_cone10")
+    lv = oracle_level(wl)
+    sim = P.Sim(wl["material"], wl["levels"])
+    sim.set_stream_shape(0, 2, 1024, 2, 1, 19)
+    assert sim.kernel_name(0).startswith("k_rows2<1024,2> tz 19"), sim.kernel_name(0)
+    sim.run_steps(3)
+    N = lv["nx"] * lv["ny"] * lv["nz"]
+    m_ref, mb = orc.run(lv, 1, 0, 3, np.tile([0.0, 0.0, 1.0], (N, 1)), u=orc.make_axes(lv))
+    d = np.abs(gpu_state(sim) - m_ref).max()
+    assert d <= 1e-5, d
+    _, mh, _ = sim.loop(0, 0)
+    assert np.abs(mh[:4] - mb).max() <= 2e-6
+    sim.close()
+
+
+def test_rod_ensemble_full_size_bench_configuration(P, orc):
+    # the 8-realization b = 1 rod on the plan the tuner picks for the
+    # benchmark (slab), 200 steps, the last realization against the oracle
+    wl = W.workload("rod_b1_ens8")
+    lv = oracle_level(wl)
+    sim = P.Sim(wl["material"], wl["levels"])
+    assert sim.kernel_name(0).startswith("k_slab"), sim.kernel_name(0)
+    sim.run_steps(200)
+    N = lv["nx"] * lv["ny"] * lv["nz"]
+    m_ref, mb = orc.run(lv, 8, 0, 200, np.tile([0.0, 0.0, 1.0], (N, 1)))
+    assert np.abs(gpu_state(sim, 0, 7) - m_ref).max() <= 1e-5
+    _, mh, _ = sim.loop(0, 7)
+    assert np.abs(mh[:201] - mb).max() <= 2e-6
+    sim.close()
