@@ -330,7 +330,8 @@ def _loop_function():
         def forward(ctx, K, A, alpha, ms_scale, material, level, ckpt_every=256):
             mat = dict(material, K0=float(K), A0=float(A), ms_scale=float(ms_scale), scale_AK=False,
                        sr_ref_Oe_per_ns=0.0)
-            lvd = dict(level, alpha=float(alpha))
+            # the adjoint weights every step of the loop: record every step
+            lvd = dict(level, alpha=float(alpha), record_every=1)
             sim = Sim(mat, [lvd], ckpt_every=ckpt_every)
             sim.run_sweep()
             st = sim.loop(0, -1)[2]
