@@ -161,6 +161,26 @@ def test_triangle_schedule(orc):
     assert np.allclose(np.abs(d), 4 * lv["Hmax_Oe"] * lv["hscale"] / N, rtol=1e-9)
 
 
+def test_cosine_schedule(orc):
+    # the paper's sinusoidal field (protocol paragraph) started at +Hmax:
+    # extremes and zeros at the quarter periods, symmetric about the half
+    # period, and the mean |dH/dt| over a cycle equal to the sweep rate
+    # SR = 4 Hmax f (Hmax, SR as the workload gives them)
+    wl = W.workload("rod_sine_sr250_ens100")
+    lv = gk.compile_level(wl["material"], wl["levels"][0], 0)
+    N, A = lv["n_period"], lv["hz_amp"]
+    assert orc.applied_field(lv, 0) == pytest.approx(A, rel=1e-15)
+    assert orc.applied_field(lv, N // 2) == pytest.approx(-A, rel=1e-15)
+    assert abs(orc.applied_field(lv, N // 4)) < 1e-9 * A
+    assert abs(orc.applied_field(lv, 3 * N // 4)) < 1e-9 * A
+    for n in (1, 12345, N // 3, N // 2 - 7):
+        assert orc.applied_field(lv, n) == pytest.approx(orc.applied_field(lv, N - n), rel=1e-12, abs=1e-9)
+    H = orc.field_schedule_Oe(lv)
+    assert len(H) == N + 1
+    mean_rate = np.abs(np.diff(H)).sum() / (N * lv["dt"]) / 1e9          # Oe/ns
+    assert mean_rate == pytest.approx(wl["material"]["sweep_Oe_per_ns"] * lv["hscale"], rel=1e-9)
+
+
 def _langevin(x):
     return 1 / math.tanh(x) - 1 / x
 
