@@ -26,6 +26,8 @@
 // (their m' is needed only as a vertical neighbour).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "sllg_device.hpp"
 #include "sllg_types.hpp"
 
@@ -112,6 +114,21 @@ __global__ __launch_bounds__(NT) void k_rows2(
     const __amdgpu_buffer_rsrc_t r_ax = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(ax), 0, region, kBufDword3);
     const __amdgpu_buffer_rsrc_t r_ck = __builtin_amdgcn_make_buffer_rsrc(do_ckpt ? cp : mo, 0, region, kBufDword3);
     auto plane_ofs = [&](int z) { return static_cast<uint32_t>(min(z, nz - 1)) * static_cast<uint32_t>(nxy) * 4u; };
+    // (plane z given within the grid: a second clamp would be merged with the
+    // caller's into a vector min3, and a vector plane offset turns each load
+    // into a loop over distinct values)
+    auto ldc = [&](int z, uint32_t off) -> V3 {
+        const uint32_t pz = static_cast<uint32_t>(z) * static_cast<uint32_t>(nxy) * 4u;
+        return V3{__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r_in, off, pz, 0)),
+                  __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r_in, off, pz + 4u * N, 0)),
+                  __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r_in, off, pz + 8u * N, 0))};
+    };
+    auto lduc = [&](int z, uint32_t off) -> V3 {
+        const uint32_t pz = static_cast<uint32_t>(z) * static_cast<uint32_t>(nxy) * 4u;
+        return V3{__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r_ax, off, pz, 0)),
+                  __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r_ax, off, pz + 4u * N, 0)),
+                  __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r_ax, off, pz + 8u * N, 0))};
+    };
     auto ld = [&](int z, uint32_t off) -> V3 {
         const uint32_t pz = plane_ofs(z);
         return V3{__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r_in, off, pz, 0)),
@@ -142,37 +159,41 @@ __global__ __launch_bounds__(NT) void k_rows2(
     auto ym = [&](int i, int e) { return (e & 4) ? i - nx : i; };
     auto yp = [&](int i, int e) { return (e & 8) ? i + nx : i; };
 
-    V3 B[K], Cn[K], Dn[K];                // m_n of planes p, p+1, p+2
-    V3 UA[K], UB[K], UC[K];               // axes of planes p-1, p, p+1
-    V3 qm1[K], hm1[K];                    // q, H_th of plane p-1
-    V3 mpm2[K];                           // m' of plane p-2 (own cells)
-    V3 EB{0, 0, 0}, EC{0, 0, 0}, ED{0, 0, 0};   // extra row: planes p, p+1, p+2
+    // The z-columns rotate with period 3 (m_n of p, p+1, p+2; axes of p-1, p,
+    // p+1; q and H_th of the plane before): the plane loop is unrolled three
+    // times and slot (p - pz0) % 3 of each array is renamed, not copied.
+    V3 M[3][K];          // m_n: slot PH = plane p, PH+1 = p+1, PH+2 = p+2
+    V3 U[3][K];          // axes: slot PH = plane p-1, PH+1 = p, PH+2 = p+1
+    V3 Q[3][K], HT[3][K];   // q, H_th: slot PH = plane p, PH+2 = plane p-1
+    V3 mpm2[K];          // m' of plane p-2 (own cells)
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        B[j] = Cn[j] = Dn[j] = UA[j] = UB[j] = UC[j] = V3{0, 0, 0};
-        qm1[j] = hm1[j] = mpm2[j] = V3{0, 0, 0};
-        if (!on[j]) continue;
-        if (pz0 > 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) M[k][j] = U[k][j] = Q[k][j] = HT[k][j] = V3{0, 0, 0};
+        mpm2[j] = V3{0, 0, 0};
+        if (pz0 > 0 && on[j]) {
             // plane pz0 - 1 of the own column, the lower neighbour of the first plane
             Mn0[((pz0 - 1) & 1) * LC + ii[j] + nx] = f4(ld(pz0 - 1, gb[j]));
         }
-        B[j] = ld(pz0, gb[j]);
-        Cn[j] = ld(pz0 + 1, gb[j]);
-        Dn[j] = ld(pz0 + 2, gb[j]);
+        M[0][j] = ld(pz0, gb[j]);
+        M[1][j] = ld(pz0 + 1, gb[j]);
+        M[2][j] = ld(pz0 + 2, gb[j]);
         if (AXES) {
-            UB[j] = ldu(pz0, gb[j]);
-            UC[j] = ldu(pz0 + 1, gb[j]);
+            U[1][j] = ldu(pz0, gb[j]);
+            U[2][j] = ldu(pz0 + 1, gb[j]);
         }
     }
-    if (ex) {
-        EB = ld(pz0, ex_gb);
-        EC = ld(pz0 + 1, ex_gb);
-        ED = ld(pz0 + 2, ex_gb);
-    }
+    // the extra rows of plane p go to LDS during plane p - 1 (below), loaded
+    // at the end of plane p - 2; those of the first plane here
+    if (ex) Mn0[(pz0 & 1) * LC + ex_li] = f4(ld(pz0, ex_gb));
+    V3 e_next = ld(pz0 + 1, ex_gb);
 
     float msum = 0.0f;
+    const int zlast = min(pz1 + 1, nz - 1);    // the last plane of m_n the tile reads
     const int plast = zend == nz ? nz : pz1;   // the last plane holds only a corrector when zend = nz
-    for (int p = pz0; p <= plast; ++p) {
+    auto plane = [&](auto phase, const int p) {
+        constexpr int PH = decltype(phase)::value;
+        constexpr int P1 = (PH + 1) % 3, P2 = (PH + 2) % 3;
         const bool predict = p <= pz1;
         const bool halo_plane = p < z0 || p >= zend;
         const int b = p & 1;
@@ -185,25 +206,32 @@ __global__ __launch_bounds__(NT) void k_rows2(
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 if (!on[j]) continue;
-                Mn[ii[j] + nx] = f4(B[j]);
+                Mn[ii[j] + nx] = f4(M[PH][j]);
             }
-            if (ex) Mn[ex_li] = f4(EB);
         }
         lds_barrier();
         // ---- 2. predictor at plane p; 3. m'(p) to LDS
-        V3 mpn[K], qn[K], hn[K];
+        // (a cell that is not predicted here is not corrected from this plane
+        // either, so its m', q and H_th slots are left as they are)
+        V3 mpn[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            mpn[j] = qn[j] = hn[j] = V3{0, 0, 0};
             if (!predict || !on[j] || (halo_plane && !win[j])) continue;
-            const V3 m = B[j];
+            const V3 m = M[PH][j];
             const int l = ii[j] + nx, e = edge[j];
             const V3 exs = nb_sum(m, v34(Mn[xm(l, e)]), v34(Mn[xp(l, e)]), v34(Mn[ym(l, e)]), v34(Mn[yp(l, e)]),
-                                  p > 0 ? v34(Mo[l]) : m, p < nz - 1 ? Cn[j] : m);
-            hn[j] = thermal_field(L, I.seed, static_cast<uint32_t>((ii[j] + gofs) + nxy * p), n);
-            heun_predict(L, m, exs, AXES ? UB[j] : u0, hz0, hn[j], mpn[j], qn[j]);
+                                  p > 0 ? v34(Mo[l]) : m, p < nz - 1 ? M[P1][j] : m);
+            HT[PH][j] = thermal_field(L, I.seed, static_cast<uint32_t>((ii[j] + gofs) + nxy * p), n);
+            heun_predict(L, m, exs, AXES ? U[P1][j] : u0, hz0, HT[PH][j], mpn[j], Q[PH][j]);
             Mp[ii[j]] = f4(mpn[j]);
         }
+        // ---- the extra rows of plane p + 1 into the m_n buffer of plane
+        //      p - 1, whose extra rows nobody reads after the barrier above.
+        //      (Before the corrector's stores, so that the wait for the load
+        //      does not include them; the empty asm uses the loaded values in
+        //      every wave, so that the wait is taken here whichever lanes store.)
+        asm volatile("" ::"v"(e_next.x), "v"(e_next.y), "v"(e_next.z));
+        if (ex && p + 1 <= pz1) Mn0[(b ^ 1) * LC + ex_li] = f4(e_next);
         // ---- 4. corrector at plane p - 1
         const int cz = p - 1;
         if (cz >= z0 && cz < zend) {
@@ -214,32 +242,37 @@ __global__ __launch_bounds__(NT) void k_rows2(
                 const V3 mpc = v34(Mq[i]);
                 const V3 exs = nb_sum(mpc, v34(Mq[xm(i, e)]), v34(Mq[xp(i, e)]), v34(Mq[ym(i, e)]), v34(Mq[yp(i, e)]),
                                       cz > 0 ? mpm2[j] : mpc, predict ? mpn[j] : mpc);
-                const V3 mn1 = heun_correct(L, mpc, exs, AXES ? UA[j] : u0, hz1, hm1[j], qm1[j]);
+                const V3 mn1 = heun_correct(L, mpc, exs, AXES ? U[PH][j] : u0, hz1, HT[P2][j], Q[P2][j]);
                 st3(r_out, cz, gb[j], mn1);
                 msum += mn1.z;
                 if (do_ckpt) st3(r_ck, cz, gb[j], v34(Mo[ii[j] + nx]));
             }
         }
-        // ---- 5. shift the columns; loads of plane p + 3 and axes of p + 2
+        // ---- 5. m'(p - 1) becomes the lower neighbour of the next corrector;
+        //         loads of plane p + 3 into the slot of plane p, of the axes of
+        //         plane p + 2 into the slot of plane p - 1 and of the extra
+        //         rows of plane p + 2
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            qm1[j] = qn[j];
-            hm1[j] = hn[j];
-            mpm2[j] = v34(Mq[ii[j]]);   // m'(p - 1), the lower neighbour of the next corrector
-            B[j] = Cn[j];
-            Cn[j] = Dn[j];
-            if (on[j] && p + 3 <= pz1 + 1) Dn[j] = ld(p + 3, gb[j]);
-            if (AXES) {
-                UA[j] = UB[j];
-                UB[j] = UC[j];
-                if (on[j] && p + 2 <= pz1) UC[j] = ldu(p + 2, gb[j]);
-            }
+            // The loads are unconditional, so that the compiler can count the
+            // memory operations in flight exactly and wait only for the ones a
+            // value needs: past the last plane a tile uses they repeat that
+            // plane (a cache hit), and lanes without a cell read at offset 0.
+            mpm2[j] = v34(Mq[ii[j]]);
+            M[PH][j] = ldc(min(p + 3, zlast), gb[j]);
+            if (AXES) U[PH][j] = lduc(min(p + 2, pz1), gb[j]);
         }
-        if (ex) {
-            EB = EC;
-            EC = ED;
-            if (p + 3 <= pz1) ED = ld(p + 3, ex_gb);
-        }
+        e_next = ldc(min(p + 2, pz1), ex_gb);
+    };
+    // the first loads complete before the loop, so that the wait counts in
+    // the loop follow its own loads only
+    __builtin_amdgcn_s_waitcnt(0);
+    for (int p = pz0; p <= plast; p += 3) {
+        plane(std::integral_constant<int, 0>{}, p);
+        if (p + 1 > plast) break;
+        plane(std::integral_constant<int, 1>{}, p + 1);
+        if (p + 2 > plast) break;
+        plane(std::integral_constant<int, 2>{}, p + 2);
     }
 
     const double tot = block_sum<NT>(msum, red);

@@ -122,7 +122,13 @@ def test_decimated_records(P, plan):
     assert len(m2) == 5003 // 10 + 1
     assert np.array_equal(m2, m1[::10][:len(m2)])
     assert np.array_equal(H2, H1[::10][:len(m2)])
-    assert s2["S_sim"] == s1["S_sim"]          # area uses every step either way
+    # the area uses every step either way; the slab plan folds each launch's
+    # steps in parallel, so different launch boundaries (3003 + 2000 steps
+    # against 5003) sum the same FP64 terms in another order
+    if plan == "slab":
+        assert s2["S_sim"] == pytest.approx(s1["S_sim"], rel=1e-13)
+    else:
+        assert s2["S_sim"] == s1["S_sim"]
     full.close()
     dec.close()
 
