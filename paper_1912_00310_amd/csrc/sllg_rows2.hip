@@ -49,7 +49,15 @@ __global__ __launch_bounds__(NT) void k_rows2(
     __shared__ double red[NT / 64];
 
     const int tid = threadIdx.x;
-    const int tile = tile_base + static_cast<int>(blockIdx.x);
+    // Workgroups go to the 8 XCDs round-robin by block index; block b runs
+    // tile start(b % 8) + b / 8, so that each XCD takes a contiguous run of
+    // the tile list (neighbouring y windows of one z range), whose shared
+    // rows then come from that XCD's L2.  A bijection for any grid size.
+    const int tile = [] {
+        const int nb = static_cast<int>(gridDim.x), b = static_cast<int>(blockIdx.x);
+        const int x = b % 8;
+        return x * (nb / 8) + min(x, nb % 8) + b / 8;
+    }() + tile_base;
     const TileDev T = tiles[tile];
     const InstDev I = insts[T.inst];
     const LevelDev& L = levels[I.level];
