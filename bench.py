@@ -32,12 +32,15 @@ if ROOT not in sys.path:
 
 METRIC = "sLLG cell-updates/s & loops/s at 1 GPU (% HBM roofline); batched & adjoint vs plain"
 
-# Algorithmic work of one cell-update (one Heun step of one cell); derivation
-# in the design doc.  Lane operations counted at one per VALU op (an FMA is one):
-# Philox4x32-10 (20 wide multiplies + 40 xors), four 23-bit uniforms, the
-# Box-Muller transform, two effective fields, two LLG right-hand sides, the
-# predictor/corrector updates and two renormalisations.
-VALU_OPS_PER_CELL_UPDATE = 240
+# Algorithmic work of one cell-update (one Heun step of one cell), counted as
+# the VALU instructions of the per-cell device functions compiled alone for
+# gfx950, without load addressing (an FMA or a transcendental is one):
+# Philox4x32-10 (18 wide multiplies, 19 exclusive-ors, most of them
+# three-input), four 23-bit uniforms (8), Box-Muller (12, 7 of them
+# transcendental), the thermal field scale (3), two neighbour sums (2 x 18),
+# two effective fields, two LLG right-hand sides, the predictor and corrector
+# updates and two renormalisations: 120 in the predictor, 57 in the corrector.
+VALU_OPS_PER_CELL_UPDATE = 177
 # HBM: m_n in and m_{n+1} out (12 + 12 bytes); per-cell easy axes add 12.
 BYTES_PER_CELL_UPDATE = 24
 BYTES_AXES = 12
