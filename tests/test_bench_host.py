@@ -1,0 +1,42 @@
+"""Host-side pieces of bench.py: the committed HBM-traffic summaries are found
+under the dominant kernel's template name and are used only while the kernel
+sources are the ones they were measured on."""
+import glob
+import os
+
+import bench
+
+
+def _kv(path):
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    return kv
+
+
+def test_traffic_summaries_are_found_by_kernel_template_name():
+    files = glob.glob(os.path.join(bench.ROOT, "profiles", "*_traffic.txt"))
+    assert files
+    for path in files:
+        kv = _kv(path)
+        stem = os.path.basename(path)[: -len("_traffic.txt")]
+        kernel = kv["kernel"].split("<")[0]
+        assert stem.startswith(kernel + "_"), (path, kernel)
+        workload = stem[len(kernel) + 1:]
+        got = bench.measured_traffic(kernel, workload)
+        if kv["source_sha256"] == bench.source_digest():
+            assert got == int(float(kv["hbm_bytes_per_launch"]))
+        else:
+            assert got is None
+        # the scaled counters (printed to 0.1 KiB and 6 digits) give the total
+        hbm = (float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
+               + float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])) * 1024
+        assert abs(hbm - float(kv["hbm_bytes_per_launch"])) <= 1e-4 * hbm
+
+
+def test_unknown_kernel_or_workload_has_no_traffic():
+    assert bench.measured_traffic("k_nonexistent", "rod_b1_ens8") is None
+    assert bench.measured_traffic("k_slab", "no_such_workload") is None
