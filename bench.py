@@ -183,7 +183,7 @@ def main():
         gbs = per_launch * bpc / (launch_ms * 1e-3) / 1e9
         tops = per_launch * VALU_OPS_PER_CELL_UPDATE / (launch_ms * 1e-3) / 1e12
         f_h, f_a = gbs / PEAK_HBM_GBS, tops / PEAK_VALU_TOPS
-        traffic = measured_traffic(dom.split("<")[0], a.workload)
+        traffic = measured_traffic(dom, a.workload)
         # streamed kernels move the state through HBM every step; the slab and
         # resident kernels keep it on chip (LDS) and are bound by arithmetic
         # and latency, so their fraction is taken against the ALU peak
@@ -294,12 +294,23 @@ def source_digest():
     return h.hexdigest()
 
 
+def kernel_instance(name):
+    """'k_rows2<1024,1> tz 43' or 'k_rows2<1024,1,true>' -> 'k_rows2<1024,1'
+    (template and its thread and cell counts; the axes flag follows the
+    workload)."""
+    n = name.split()[0].replace(" ", "")
+    for flag in (",true>", ",false>"):
+        n = n.replace(flag, ">")
+    return n.rstrip(">")
+
+
 def measured_traffic(kernel, workload):
-    """HBM bytes per launch of the dominant kernel (template name, e.g.
-    k_rows2) from the committed counter summary (FETCH_SIZE + WRITE_SIZE
-    scaled by a plain copy of known size), or None when there is none or the
-    kernel sources changed since."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+    """HBM bytes per launch of the dominant kernel (as the library names it,
+    e.g. 'k_rows2<1024,1> tz 43') from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size), or None
+    when there is none, it was taken on another instantiation, or the kernel
+    sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"{kernel.split('<')[0]}_{workload}_traffic.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -309,6 +320,8 @@ def measured_traffic(kernel, workload):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
     if kv.get("source_sha256") != source_digest():
+        return None
+    if "<" in kernel and kernel_instance(kv.get("kernel", "")) != kernel_instance(kernel):
         return None
     try:
         return int(float(kv["hbm_bytes_per_launch"]))

@@ -26,7 +26,10 @@ def test_traffic_summaries_are_found_by_kernel_template_name():
         kernel = kv["kernel"].split("<")[0]
         assert stem.startswith(kernel + "_"), (path, kernel)
         workload = stem[len(kernel) + 1:]
-        got = bench.measured_traffic(kernel, workload)
+        # as the library names the dominant kernel in the bench line
+        inst = bench.kernel_instance(kv["kernel"]) + "> tz 7"
+        got = bench.measured_traffic(inst, workload)
+        assert bench.measured_traffic(kernel + "<1,1> tz 7", workload) is None   # another instantiation
         if kv["source_sha256"] == bench.source_digest():
             assert got == int(float(kv["hbm_bytes_per_launch"]))
         else:
@@ -35,6 +38,13 @@ def test_traffic_summaries_are_found_by_kernel_template_name():
         hbm = (float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
                + float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])) * 1024
         assert abs(hbm - float(kv["hbm_bytes_per_launch"])) <= 1e-4 * hbm
+
+
+def test_kernel_instance_names():
+    assert bench.kernel_instance("k_rows2<1024,1> tz 43") == "k_rows2<1024,1"
+    assert bench.kernel_instance("k_rows2<1024,1,true>") == "k_rows2<1024,1"
+    assert bench.kernel_instance("k_slab<1024,1> tz 2 steps/launch 1024") == bench.kernel_instance("k_slab<1024,1>")
+    assert bench.kernel_instance("k_slab<768,2>") != bench.kernel_instance("k_slab<1024,1>")
 
 
 def test_unknown_kernel_or_workload_has_no_traffic():
