@@ -311,14 +311,17 @@ def test_rows2_bit_identical_to_window_kernel(P, cone):
 
 
 # ---- full-size workloads in the launch configuration the benchmark times
-def test_block_full_size_bench_configuration(P, orc):
-    # the 128 x 128 x 512 block with k_rows2<1024,2> and 19 planes per tile,
-    # three steps against the FP64 oracle over all 8.4M cells
+@pytest.mark.parametrize("cells,planes", [(1, 43), (2, 19)])
+def test_block_full_size_bench_configuration(P, orc, cells, planes):
+    # the 128 x 128 x 512 block on the two tile kernels the tuner picks
+    # between for the benchmark (k_rows2<1024,1>, 43 planes per tile, and
+    # k_rows2<1024,2>, 19 planes), three steps against the FP64 oracle over
+    # all 8.4M cells
     wl = W.workload("block_b2_cone10")
     lv = oracle_level(wl)
     sim = P.Sim(wl["material"], wl["levels"])
-    sim.set_stream_shape(0, 2, 1024, 2, 1, 19)
-    assert sim.kernel_name(0).startswith("k_rows2<1024,2> tz 19"), sim.kernel_name(0)
+    sim.set_stream_shape(0, 2, 1024, cells, 1, planes)
+    assert sim.kernel_name(0).startswith(f"k_rows2<1024,{cells}> tz {planes}"), sim.kernel_name(0)
     sim.run_steps(3)
     N = lv["nx"] * lv["ny"] * lv["nz"]
     m_ref, mb = orc.run(lv, 1, 0, 3, np.tile([0.0, 0.0, 1.0], (N, 1)), u=orc.make_axes(lv))
