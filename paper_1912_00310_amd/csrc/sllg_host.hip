@@ -547,30 +547,49 @@ int build_resident(sllg_ctx* C)
         std::stable_sort(inst.begin(), inst.end(), [&](int a, int b) {
             return C->lv[C->h_insts[a].level].ncell > C->lv[C->h_insts[b].level].ncell;
         });
-        // number of groups: one instance per group up to two per CU, else pack
-        // (more groups while a group would exceed the chunk or LDS limit)
-        int ng = (int)std::min<int64_t>(total, 2LL * C->num_cus);
-        if (total > 2LL * C->num_cus) ng = C->num_cus;
+        // Instances go, largest first, to the group with the fewest chunks so
+        // far (ties to the lowest index).  Number of groups: one instance per
+        // group up to two per CU, else pack (more groups while a group would
+        // exceed the chunk or LDS limit).  Between one and two instances per
+        // CU, one group per CU is taken instead when the extra instances fit
+        // beside others without any group outgrowing the largest instance:
+        // a step then costs what the largest instance costs alone, without
+        // two workgroups sharing a CU.
         std::vector<std::vector<int>> members;
         int64_t max_chunks = 0, max_lds = 0, max_cells = 0;
-        for (;;) {
-            members.assign(ng, {});
-            std::vector<int64_t> load(ng, 0), lds(ng, 0);
+        auto pack = [&](int ngr) {
+            members.assign(ngr, {});
+            std::vector<int64_t> load(ngr, 0), lds(ngr, 0);
             for (size_t k = 0; k < inst.size(); ++k) {
-                // round-robin over the groups (instances sorted by size)
-                int g = (int)(k % ng);
+                int g = 0;
+                for (int q = 1; q < ngr; ++q)
+                    if (load[q] < load[g]) g = q;
                 const LevelHost& h = C->lv[C->h_insts[inst[k]].level];
                 members[g].push_back(inst[k]);
                 load[g] += ceil_div(h.ncell, 64);
                 lds[g] += 24 * h.ncell;
             }
             max_chunks = max_lds = max_cells = 0;
-            for (int g = 0; g < ng; ++g) {
+            for (int g = 0; g < ngr; ++g) {
                 max_chunks = std::max(max_chunks, load[g]);
                 max_cells = std::max(max_cells, lds[g] / 24);
                 max_lds = std::max<int64_t>(max_lds, lds[g] + 8 * load[g] + 48 +
                                                          (int64_t)(sizeof(AccDev) + 16) * members[g].size());
             }
+        };
+        int ng = (int)std::min<int64_t>(total, 2LL * C->num_cus);
+        if (total > 2LL * C->num_cus) ng = C->num_cus;
+        bool packed = false;
+        if (total > C->num_cus && total <= 2LL * C->num_cus) {
+            const int64_t largest = ceil_div(C->lv[C->h_insts[inst[0]].level].ncell, 64);
+            pack(C->num_cus);
+            if (max_chunks <= largest && max_lds <= C->max_lds) {
+                ng = C->num_cus;
+                packed = true;
+            }
+        }
+        while (!packed) {
+            pack(ng);
             if ((max_chunks <= kResMaxChunks && max_lds <= C->max_lds) || ng >= total) break;
             ng = (int)std::min<int64_t>(total, 2LL * ng);
         }
