@@ -5,25 +5,28 @@
 // the planes [z0, z0 + nzt).  It predicts the window plus one ring row on
 // each side that lies inside the grid (rows [py0, py1)); the cells of that
 // region are dealt to the threads in row-major order, K per thread, and a
-// thread keeps its cells' whole z-columns: m_n of planes p-1, p, p+1 and the
-// plane p+2 in flight, the easy axes of p-1, p, p+1, q and H_th of the
-// previous plane and m' of the plane before.  LDS holds only x-y planes, one
-// float4 per cell: m_n of planes p and p - 1 (the predicted rows plus the rows
-// py0 - 1 and py1, loaded by the first 2*nx threads) and m' of planes p and
-// p - 1; every buffer is written once per plane and read by other threads
-// only until the next barrier, so one barrier per plane suffices, and a
-// thread reads its own column's previous plane back from LDS.  Global
-// accesses are buffer instructions with 32-bit offsets.  At plane p the
-// workgroup
+// thread keeps its cells' z-columns in registers: m_n of planes p, p+1 and
+// p+2 (the load of p+3 is issued during plane p), the easy axes of p-1, p and
+// p+1, q and H_th of the plane before and m' of the plane before that.  The
+// three-plane columns rotate by renaming: the plane loop is unrolled three
+// times.  LDS holds only x-y planes, one float4 per cell: m_n of planes p and
+// p - 1 (the predicted rows plus the rows py0 - 1 and py1, which the first
+// 2*nx threads load two planes ahead) and m' of planes p and p - 1; every
+// buffer is written once per plane and read by other threads only until the
+// next barrier, so one barrier per plane suffices, and a thread reads its
+// own column's previous plane back from LDS.  Global accesses are buffer
+// instructions with 32-bit offsets.  At plane p the workgroup
 //   1. writes m_n(p) to LDS and waits at the barrier,
 //   2. predicts plane p from LDS (x-y) and registers (z),
-//   3. writes m'(p) to the other LDS buffer,
+//   3. writes m'(p) to the other LDS buffer, and the extra rows of plane
+//      p + 1 into the m_n buffer of plane p - 1,
 //   4. corrects plane p - 1 from m'(p - 1) in LDS (x-y) and registers (z),
 //      storing m_{n+1},
-//   5. shifts its registers and issues the loads of plane p + 3 (and the
-//      axes of plane p + 2).
+//   5. issues the loads of plane p + 3, of the axes of plane p + 2 and of
+//      the extra rows of plane p + 2.
 // The planes z0 - 1 and z0 + nzt are predicted for the window cells only
-// (their m' is needed only as a vertical neighbour).
+// (their m' is needed only as a vertical neighbour).  Workgroups are dealt to
+// the XCDs so that each XCD runs a contiguous part of the tile list.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
