@@ -90,6 +90,21 @@ __global__ __launch_bounds__(NT) void k_rows2(
     float* cp = do_ckpt ? ckpt + I.ckpt_off + (n / ckpt_every) * 3 * static_cast<int64_t>(N) : nullptr;
     const float* ax = axes + L.axes_off;
     const V3 u0 = V3{L.ux, L.uy, L.uz};
+    // The step constants, in vector registers with one cell per thread (a
+    // scalar reload inside the loop waits on the same counter as the plane's
+    // LDS reads); with two cells per thread the registers are needed elsewhere.
+    LevelDev Lv{};
+    if constexpr (K == 1) {
+        Lv = L;
+        Lv.c_ex = vreg(L.c_ex);
+        Lv.hk = vreg(L.hk);
+        Lv.g1 = vreg(L.g1);
+        Lv.ag1 = vreg(L.ag1);
+        Lv.dt = vreg(L.dt);
+        Lv.half_dt = vreg(L.half_dt);
+        Lv.sigma = vreg(L.sigma);
+    }
+    const LevelDev& Lc = K == 1 ? Lv : L;
 
     // own cells: index ii in the predicted region (the m' plane index; the
     // m_n LDS index is ii + nx, the plane index ii + py0 nx) and which x-y
@@ -230,10 +245,23 @@ __global__ __launch_bounds__(NT) void k_rows2(
             if (!predict || !on[j] || (halo_plane && !win[j])) continue;
             const V3 m = M[PH][j];
             const int l = ii[j] + nx, e = edge[j];
-            const V3 exs = nb_sum(m, v34(Mn[xm(l, e)]), v34(Mn[xp(l, e)]), v34(Mn[ym(l, e)]), v34(Mn[yp(l, e)]),
-                                  p > 0 ? v34(Mo[l]) : m, p < nz - 1 ? M[P1][j] : m);
-            HT[PH][j] = thermal_field(L, I.seed, static_cast<uint32_t>((ii[j] + gofs) + nxy * p), n);
-            heun_predict(L, m, exs, AXES ? U[P1][j] : u0, hz0, HT[PH][j], mpn[j], Q[PH][j]);
+            const uint32_t cell = static_cast<uint32_t>((ii[j] + gofs) + nxy * p);
+            V3 exs;
+            if constexpr (K == 1) {
+                // the LDS reads are issued, then the noise is drawn while they
+                // are in flight (with two cells per thread the values held
+                // meanwhile would spill)
+                const V3 n_xm = v34(Mn[xm(l, e)]), n_xp = v34(Mn[xp(l, e)]);
+                const V3 n_ym = v34(Mn[ym(l, e)]), n_yp = v34(Mn[yp(l, e)]);
+                const V3 n_zm = p > 0 ? v34(Mo[l]) : m;
+                HT[PH][j] = thermal_field(Lc, I.seed, cell, n);
+                exs = nb_sum(m, n_xm, n_xp, n_ym, n_yp, n_zm, p < nz - 1 ? M[P1][j] : m);
+            } else {
+                exs = nb_sum(m, v34(Mn[xm(l, e)]), v34(Mn[xp(l, e)]), v34(Mn[ym(l, e)]), v34(Mn[yp(l, e)]),
+                             p > 0 ? v34(Mo[l]) : m, p < nz - 1 ? M[P1][j] : m);
+                HT[PH][j] = thermal_field(Lc, I.seed, cell, n);
+            }
+            heun_predict(Lc, m, exs, AXES ? U[P1][j] : u0, hz0, HT[PH][j], mpn[j], Q[PH][j]);
             Mp[ii[j]] = f4(mpn[j]);
         }
         // ---- the extra rows of plane p + 1 into the m_n buffer of plane
@@ -253,7 +281,7 @@ __global__ __launch_bounds__(NT) void k_rows2(
                 const V3 mpc = v34(Mq[i]);
                 const V3 exs = nb_sum(mpc, v34(Mq[xm(i, e)]), v34(Mq[xp(i, e)]), v34(Mq[ym(i, e)]), v34(Mq[yp(i, e)]),
                                       cz > 0 ? mpm2[j] : mpc, predict ? mpn[j] : mpc);
-                const V3 mn1 = heun_correct(L, mpc, exs, AXES ? U[PH][j] : u0, hz1, HT[P2][j], Q[P2][j]);
+                const V3 mn1 = heun_correct(Lc, mpc, exs, AXES ? U[PH][j] : u0, hz1, HT[P2][j], Q[P2][j]);
                 st3(r_out, cz, gb[j], mn1);
                 msum += mn1.z;
                 if (do_ckpt) st3(r_ck, cz, gb[j], v34(Mo[ii[j] + nx]));
