@@ -130,6 +130,20 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
     __syncthreads();
 
     const bool axes_on = L.has_axes != 0;
+    // step constants in vector registers with one plane per thread (a scalar
+    // reload inside the step loop waits on the same counter as LDS accesses)
+    LevelDev Lv{};
+    if constexpr (K == 1) {
+        Lv = L;
+        Lv.c_ex = vreg(L.c_ex);
+        Lv.hk = vreg(L.hk);
+        Lv.g1 = vreg(L.g1);
+        Lv.ag1 = vreg(L.ag1);
+        Lv.dt = vreg(L.dt);
+        Lv.half_dt = vreg(L.half_dt);
+        Lv.sigma = vreg(L.sigma);
+    }
+    const LevelDev& Lc = K == 1 ? Lv : L;
     const float* ax = axes + L.axes_off;
     // The thermal field of a step does not depend on m: the field of step
     // n + 1 is drawn while the boundary words of step n are in flight, and the
@@ -141,7 +155,7 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
             const int e = r + j * NPP;
             const int z = z0 - 1 + e;
             if (!lane_on || e >= NE || z < 0 || z >= nz) continue;
-            hth[j] = thermal_field(L, I.seed, static_cast<uint32_t>(c + P * z), n);
+            hth[j] = thermal_field(Lc, I.seed, static_cast<uint32_t>(c + P * z), n);
         }
     };
     draw(n0);
@@ -165,7 +179,7 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
             const int cell = c + P * z;
             u[j] = axes_on ? V3{ax[cell], ax[N + cell], ax[2 * N + cell]} : V3{L.ux, L.uy, L.uz};
             V3 mp;
-            heun_predict(L, m, ex, u[j], hz0, hth[j], mp, q[j]);
+            heun_predict(Lc, m, ex, u[j], hz0, hth[j], mp, q[j]);
             Mp[e * P + c] = f4(mp.x, mp.y, mp.z);
             if (ckpt != nullptr && ckpt_every > 0 && (n % ckpt_every) == 0 && e >= 1 && e <= nzs) {
                 float* cp = ckpt + I.ckpt_off + (n / ckpt_every) * 3 * static_cast<int64_t>(N);
@@ -189,7 +203,7 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
             const V3 mp = v34(pl[c]);
             const V3 ex = nb_sum(mp, v34(pl[ixm]), v34(pl[ixp]), v34(pl[iym]), v34(pl[iyp]),
                                  z > 0 ? v34(pl[c - P]) : mp, z < nz - 1 ? v34(pl[c + P]) : mp);
-            const V3 mnew = heun_correct(L, mp, ex, u[j], hz1, hth[j], q[j]);
+            const V3 mnew = heun_correct(Lc, mp, ex, u[j], hz1, hth[j], q[j]);
             const int me = e + 1;
             Mn[me * P + c] = f4(mnew.x, mnew.y, mnew.z);
             msum += mnew.z;
