@@ -110,8 +110,12 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
     // exchange slot (3 x P words) of one plane of one slab at a step parity
     (void)tag_base;
     uint32_t* const xch = reinterpret_cast<uint32_t*>(xch64);
+    // (the parity stride is formed once: gridDim.x read inside the step loop
+    // is a scalar load that waits on the same counter as the LDS accesses)
+    const int64_t par_stride = static_cast<int64_t>(gridDim.x) * 4 * 3 * P;
+    uint32_t* const xch_par[2] = {xch, xch + par_stride};
     auto xslot = [&](int par, int slab, int slot) {
-        return xch + ((static_cast<int64_t>(par) * gridDim.x + slab) * 4 + slot) * 3 * P;
+        return xch_par[par] + (static_cast<int64_t>(slab) * 4 + slot) * 3 * P;
     };
     const int nzs_prev = S.prev >= 0 ? slabs[S.prev].nzs : 0;
     if (tid == 0) s_abort = 0;
