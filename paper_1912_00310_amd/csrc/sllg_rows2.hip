@@ -7,7 +7,7 @@
 // region are dealt to the threads in row-major order, K per thread, and a
 // thread keeps its cells' z-columns in registers: m_n of planes p, p+1 and
 // p+2 (the load of p+3 is issued during plane p), the easy axes of p-1, p and
-// p+1, q and H_th of the plane before and m' of the plane before that.  The
+// p+1, q and H_th of the plane before, and m' of planes p, p-1 and p-2.  The
 // three-plane columns rotate by renaming: the plane loop is unrolled three
 // times.  LDS holds only x-y planes, one float4 per cell: m_n of planes p and
 // p - 1 (the predicted rows plus the rows py0 - 1 and py1, which the first
@@ -191,12 +191,12 @@ __global__ __launch_bounds__(NT) void k_rows2(
     V3 M[3][K];          // m_n: slot PH = plane p, PH+1 = p+1, PH+2 = p+2
     V3 U[3][K];          // axes: slot PH = plane p-1, PH+1 = p, PH+2 = p+1
     V3 Q[3][K], HT[3][K];   // q, H_th: slot PH = plane p, PH+2 = plane p-1
-    V3 mpm2[K];          // m' of plane p-2 (own cells)
+    V3 MP[3][K];         // m' (own cells): slot PH = plane p, PH+2 = p-1, PH+1 = p-2
 #pragma unroll
     for (int j = 0; j < K; ++j) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) M[k][j] = U[k][j] = Q[k][j] = HT[k][j] = V3{0, 0, 0};
-        mpm2[j] = V3{0, 0, 0};
+        MP[0][j] = MP[1][j] = MP[2][j] = V3{0, 0, 0};
         if (pz0 > 0 && on[j]) {
             // plane pz0 - 1 of the own column, the lower neighbour of the first plane
             Mn0[((pz0 - 1) & 1) * LC + ii[j] + nx] = f4(ld(pz0 - 1, gb[j]));
@@ -239,7 +239,6 @@ __global__ __launch_bounds__(NT) void k_rows2(
         // ---- 2. predictor at plane p; 3. m'(p) to LDS
         // (a cell that is not predicted here is not corrected from this plane
         // either, so its m', q and H_th slots are left as they are)
-        V3 mpn[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             if (!predict || !on[j] || (halo_plane && !win[j])) continue;
@@ -261,8 +260,8 @@ __global__ __launch_bounds__(NT) void k_rows2(
                              p > 0 ? v34(Mo[l]) : m, p < nz - 1 ? M[P1][j] : m);
                 HT[PH][j] = thermal_field(Lc, I.seed, cell, n);
             }
-            heun_predict(Lc, m, exs, AXES ? U[P1][j] : u0, hz0, HT[PH][j], mpn[j], Q[PH][j]);
-            Mp[ii[j]] = f4(mpn[j]);
+            heun_predict(Lc, m, exs, AXES ? U[P1][j] : u0, hz0, HT[PH][j], MP[PH][j], Q[PH][j]);
+            Mp[ii[j]] = f4(MP[PH][j]);
         }
         // ---- the extra rows of plane p + 1 into the m_n buffer of plane
         //      p - 1, whose extra rows nobody reads after the barrier above.
@@ -278,17 +277,16 @@ __global__ __launch_bounds__(NT) void k_rows2(
             for (int j = 0; j < K; ++j) {
                 if (!win[j]) continue;
                 const int i = ii[j], e = edge[j];
-                const V3 mpc = v34(Mq[i]);
+                const V3 mpc = MP[P2][j];   // the own cell's m'(p - 1), also in LDS for the neighbours
                 const V3 exs = nb_sum(mpc, v34(Mq[xm(i, e)]), v34(Mq[xp(i, e)]), v34(Mq[ym(i, e)]), v34(Mq[yp(i, e)]),
-                                      cz > 0 ? mpm2[j] : mpc, predict ? mpn[j] : mpc);
+                                      cz > 0 ? MP[P1][j] : mpc, predict ? MP[PH][j] : mpc);
                 const V3 mn1 = heun_correct(Lc, mpc, exs, AXES ? U[PH][j] : u0, hz1, HT[P2][j], Q[P2][j]);
                 st3(r_out, cz, gb[j], mn1);
                 msum += mn1.z;
                 if (do_ckpt) st3(r_ck, cz, gb[j], v34(Mo[ii[j] + nx]));
             }
         }
-        // ---- 5. m'(p - 1) becomes the lower neighbour of the next corrector;
-        //         loads of plane p + 3 into the slot of plane p, of the axes of
+        // ---- 5. loads of plane p + 3 into the slot of plane p, of the axes of
         //         plane p + 2 into the slot of plane p - 1 and of the extra
         //         rows of plane p + 2
 #pragma unroll
@@ -297,7 +295,6 @@ __global__ __launch_bounds__(NT) void k_rows2(
             // memory operations in flight exactly and wait only for the ones a
             // value needs: past the last plane a tile uses they repeat that
             // plane (a cache hit), and lanes without a cell read at offset 0.
-            mpm2[j] = v34(Mq[ii[j]]);
             M[PH][j] = ldc(min(p + 3, zlast), gb[j]);
             if (AXES) U[PH][j] = lduc(min(p + 2, pz1), gb[j]);
         }
