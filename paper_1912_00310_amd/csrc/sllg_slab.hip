@@ -168,7 +168,7 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
     for (int st = 0; st < nsteps; ++st) {
         const int64_t n = n0 + st;
         const float hz0 = s_hz[st], hz1 = s_hz[st + 1];
-        V3 q[K], u[K];
+        V3 q[K], u[K], mps[K];   // mps: the own cell's m' (also in LDS for the neighbours)
         // ---- 1. predictor on planes z0-1 .. z0+nzs
 #pragma unroll
         for (int j = 0; j < K; ++j) {
@@ -185,6 +185,7 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
             V3 mp;
             heun_predict(Lc, m, ex, u[j], hz0, hth[j], mp, q[j]);
             Mp[e * P + c] = f4(mp.x, mp.y, mp.z);
+            mps[j] = mp;
             if (ckpt != nullptr && ckpt_every > 0 && (n % ckpt_every) == 0 && e >= 1 && e <= nzs) {
                 float* cp = ckpt + I.ckpt_off + (n / ckpt_every) * 3 * static_cast<int64_t>(N);
                 cp[cell] = m.x;
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
             if (!lane_on || e < 1 || e > nzs) continue;
             const int z = z0 - 1 + e;
             const float4* pl = Mp + e * P;
-            const V3 mp = v34(pl[c]);
+            const V3 mp = mps[j];
             const V3 ex = nb_sum(mp, v34(pl[ixm]), v34(pl[ixp]), v34(pl[iym]), v34(pl[iyp]),
                                  z > 0 ? v34(pl[c - P]) : mp, z < nz - 1 ? v34(pl[c + P]) : mp);
             const V3 mnew = heun_correct(Lc, mp, ex, u[j], hz1, hth[j], q[j]);
