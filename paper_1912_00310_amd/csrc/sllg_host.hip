@@ -1248,14 +1248,20 @@ int tune_stream(sllg_ctx* C, int level)
         h.tz = c.second;
         int rc = replan(C);
         if (rc) return rc;
-        // warm-up then timed steps; state is reset afterwards
+        // warm-up then timed steps, the better of two runs (candidates a few
+        // per cent apart are told apart despite launch jitter); state is
+        // reset afterwards
         for (int r = 0; r < 2; ++r) HIP_OK(dispatch_stream(C, level));
-        HIP_OK(hipEventRecord(e0, C->stream));
-        for (int r = 0; r < reps; ++r) HIP_OK(dispatch_stream(C, level));
-        HIP_OK(hipEventRecord(e1, C->stream));
-        HIP_OK(hipEventSynchronize(e1));
-        float ms = 0;
-        HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+        float ms = 1e30f;
+        for (int run = 0; run < 2; ++run) {
+            HIP_OK(hipEventRecord(e0, C->stream));
+            for (int r = 0; r < reps; ++r) HIP_OK(dispatch_stream(C, level));
+            HIP_OK(hipEventRecord(e1, C->stream));
+            HIP_OK(hipEventSynchronize(e1));
+            float t = 0;
+            HIP_OK(hipEventElapsedTime(&t, e0, e1));
+            ms = std::min(ms, t);
+        }
         if (getenv("SLLG_TUNE_VERBOSE"))
             fprintf(stderr, "tune level %d: shape %d (%d,%d,%d,%d) tz %d tiles %d: %.2f us/step\n", level,
                     c.first, kShapes[c.first].kind, kShapes[c.first].tx, kShapes[c.first].ty,
