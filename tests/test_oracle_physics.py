@@ -72,17 +72,57 @@ def test_larmor_frequency(orc):
     assert m[0, 2] == pytest.approx(math.cos(th0), abs=1e-12)
 
 
+def _compiled_single_cell(alpha, H_Oe, T_K=0.0, K0=0.0, A0=0.0, b=1.0, dt_s=1e-15,
+                          nx=1, ny=1, nz=1):
+    """A level compiled by gk.compile_level (not built by hand): constant
+    applied field H_Oe along z, no field scaling, exchange and anisotropy as
+    given.  The physics pins below then test compile_level's gamma1, sigma
+    and dt together with the integrator."""
+    mat = dict(W.BASE_MATERIAL, A0=A0, K0=K0, T_K=T_K, Hmax_Oe=H_Oe,
+               sweep_Oe_per_ns=1.0, wave="constant", scale_AK=True, scale_H=False)
+    lvl = dict(nx=nx, ny=ny, nz=nz, b=b, n_real=1, seed_base=1, alpha=alpha,
+               dt_s=dt_s, cone_deg=0.0, axis_seed=0, record_every=1)
+    return gk.compile_level(mat, lvl, 0)
+
+
+# gamma0 = mu0 gamma_e from the printed gamma_e (text under Eq. 1) and the
+# classical mu0; written out here so that the pins do not reuse gk's constant.
+_GAMMA0_PRINTED = 4e-7 * math.pi * 1.76e11
+
+
 def test_damped_closed_form(orc):
-    H, alpha = 1000 * OE, 0.1
-    g1 = gk.GAMMA0 / (1 + alpha ** 2)
-    th0, n, dt = math.radians(150), 200000, 1e-15
-    lv = single_cell(hz=H, alpha=alpha, dt=dt)
+    # Eq. (1) in Gilbert form dm/dt = -gamma0 m x H + alpha m x dm/dt has,
+    # for a static field H along z, the textbook solution in which m
+    # precesses at omega = gamma0 H/(1 + alpha^2) while its polar angle
+    # relaxes as tan(theta/2) = tan(theta0/2) exp(-alpha omega t).  The
+    # level comes from gk.compile_level, so this pins its gamma1, the sign of
+    # the damping term and the integrator.
+    H_Oe, alpha = 1000.0, 0.1
+    H = H_Oe * 1000 / (4 * math.pi)
+    lv = _compiled_single_cell(alpha, H_Oe)
+    assert lv["sigma"] == 0.0 and lv["hk"] == 0.0 and lv["c_ex"] == 0.0
+    omega = _GAMMA0_PRINTED * H / (1 + alpha ** 2)
+    th0, n, dt = math.radians(150), 200000, lv["dt"]
+    assert dt == 1e-15
     m, _ = run1(orc, lv, [math.sin(th0), 0, math.cos(th0)], n)
     t = n * dt
-    th = 2 * math.atan(math.tan(th0 / 2) * math.exp(-alpha * g1 * H * t))
-    phi = math.remainder(g1 * H * t, 2 * math.pi)
+    th = 2 * math.atan(math.tan(th0 / 2) * math.exp(-alpha * omega * t))
+    phi = math.remainder(omega * t, 2 * math.pi)
     assert math.acos(m[0, 2]) == pytest.approx(th, abs=1e-8)
     assert abs(math.remainder(math.atan2(m[0, 1], m[0, 0]) - phi, 2 * math.pi)) < 1e-8
+
+
+def test_larmor_from_compiled_level(orc):
+    # alpha = 0: compile_level gives sigma = 0 and gamma1 = gamma0, so m
+    # precesses at the Larmor frequency gamma0 H (period 357.0 ps at 1000 Oe)
+    lv = _compiled_single_cell(0.0, 1000.0, T_K=310.0)
+    assert lv["sigma"] == 0.0
+    H = 1000.0 * 1000 / (4 * math.pi)
+    th0, n = math.radians(40), 50000
+    m, _ = run1(orc, lv, [math.sin(th0), 0, math.cos(th0)], n)
+    phi = math.atan2(m[0, 1], m[0, 0])
+    want = math.remainder(_GAMMA0_PRINTED * H * n * lv["dt"], 2 * math.pi)
+    assert abs(math.remainder(phi - want, 2 * math.pi)) < 1e-6
 
 
 def rod_b4_level(**over):
@@ -189,19 +229,21 @@ def _langevin(x):
 def test_boltzmann_equilibrium(orc, with_k):
     # Independent spins (no exchange), b = 8 cell, T = 310 K, H = 1000 Oe.
     # Brown's thermal field must give <m_z> = L(xi) and <m_x^2> = L(xi)/xi
-    # (K = 0) or the Boltzmann quadrature with the uniaxial term.
-    T, b, H = 310.0, 8.0, 1000 * OE
-    a = b * 0.839e-9
-    V = a ** 3
+    # (K = 0) or the Boltzmann quadrature with the uniaxial term.  The level
+    # (sigma, gamma1, dt, H_K) comes from gk.compile_level; the expected
+    # values use only printed inputs (a0, Ms, K0, zeta(8), T) and the
+    # Boltzmann weight, so a wrong thermal-field variance, cell volume or
+    # anisotropy constant in compile_level fails here.
+    T, b, H_Oe = 310.0, 8.0, 1000.0
+    lv = _compiled_single_cell(1.0, H_Oe, T_K=T, K0=1e4 if with_k else 0.0,
+                               b=b, dt_s=50e-15, nx=32, ny=32)
+    assert lv["c_ex"] == 0.0
+    H = H_Oe * 1000 / (4 * math.pi)
+    V = (b * 0.839e-9) ** 3
     Ms = 480e3
-    alpha, dt = 1.0, 50e-15
-    t = T / 858.0
-    K = gk.zeta(t, 8.0) ** 3 * 1e4 if with_k else 0.0
-    sigma = math.sqrt(2 * alpha * gk.KB * T / (gk.GAMMA0 * gk.MU0 * Ms * V * dt))
-    lv = single_cell(hk=2 * K / (gk.MU0 * Ms), alpha=alpha, hz=H, sigma=sigma,
-                     dt=dt, nx=32, ny=32, nz=1)
-    xi = gk.MU0 * Ms * V * H / (gk.KB * T)
-    kv = K * V / (gk.KB * T)
+    K = 0.6839 ** 3 * 1e4 if with_k else 0.0       # printed zeta(8), Eq. (9)
+    xi = 4e-7 * math.pi * Ms * V * H / (1.380649e-23 * T)
+    kv = K * V / (1.380649e-23 * T)
     assert xi == pytest.approx(3.391, abs=2e-3)
     w = lambda c: math.exp(xi * c + kv * c * c)
     Z = integrate.quad(w, -1, 1)[0]
