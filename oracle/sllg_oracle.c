@@ -217,9 +217,18 @@ static void neighbour_diff(const orc_level* L, const double* v, int x, int y,
         for (int c = 0; c < 3; ++c) out[c] += v[3 * nb[k] + c] - v[3 * i + c];
 }
 
+/* Grids of at least this many cells spread their per-cell loops over the
+ * OpenMP threads (each cell is computed independently, so the result does not
+ * depend on the thread count).  Inside a parallel region over realizations
+ * these loops run on the calling thread only (no nested parallelism). */
+#define ORC_CELL_PAR 65536
+
 void orc_effective_field(const orc_level* L, const double* u, const double* m,
                          double hz, const double* hth, double* H)
 {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) if ((int64_t)L->nx * L->ny * L->nz >= ORC_CELL_PAR)
+#endif
     for (int z = 0; z < L->nz; ++z)
         for (int y = 0; y < L->ny; ++y)
             for (int x = 0; x < L->nx; ++x) {
@@ -264,6 +273,9 @@ static void thermal_field(const orc_level* L, uint64_t seed, int64_t n,
                           double* hth, double* xi_out)
 {
     int64_t N = (int64_t)L->nx * L->ny * L->nz;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) if (N >= ORC_CELL_PAR)
+#endif
     for (int64_t i = 0; i < N; ++i) {
         double xi[3] = {0.0, 0.0, 0.0};
         if (L->sigma != 0.0 || xi_out)
@@ -309,6 +321,9 @@ static void heun_step_ws(const orc_level* L, const double* u, uint64_t seed,
     double hz1 = orc_applied_field(L, n + 1);
     thermal_field(L, seed, n, w->hth, w->xi);
     orc_effective_field(L, u, m, hz0, w->hth, w->H);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) if (N >= ORC_CELL_PAR)
+#endif
     for (int64_t i = 0; i < N; ++i) {
         llg_rhs(L, m + 3 * i, w->H + 3 * i, w->f + 3 * i);
         double p[3];
@@ -318,6 +333,9 @@ static void heun_step_ws(const orc_level* L, const double* u, uint64_t seed,
         for (int c = 0; c < 3; ++c) w->mp[3 * i + c] = p[c] / pn;
     }
     orc_effective_field(L, u, w->mp, hz1, w->hth, w->Hp);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) if (N >= ORC_CELL_PAR)
+#endif
     for (int64_t i = 0; i < N; ++i) {
         llg_rhs(L, w->mp + 3 * i, w->Hp + 3 * i, w->fp + 3 * i);
         double q[3];
@@ -399,7 +417,10 @@ int orc_run(const orc_level* L, const double* u, uint64_t seed, int64_t n0,
     return 0;
 }
 
-/* Many realizations from the all-+z state, one thread per realization.
+/* Many realizations from the all-+z state.  With at least as many
+ * realizations as threads, one thread per realization; with fewer, the
+ * realizations run one after another and each step's cell loops use all
+ * threads.  Either way every realization's arithmetic is the same.
  * mbar: nreal x (nsteps+1); m_final (optional): nreal x 3N. */
 int orc_run_batch(const orc_level* L, const double* u, const uint64_t* seeds,
                   int32_t nreal, int64_t nsteps, double* mbar, double* m_final,
@@ -407,9 +428,11 @@ int orc_run_batch(const orc_level* L, const double* u, const uint64_t* seeds,
 {
     int64_t N = (int64_t)L->nx * L->ny * L->nz;
     int err = 0;
+    int per_real = 1;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
-#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+    per_real = nreal >= omp_get_max_threads() || N < ORC_CELL_PAR;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err) if (per_real)
 #endif
     for (int32_t r = 0; r < nreal; ++r) {
         double* m = (double*)malloc(sizeof(double) * (size_t)(3 * N));

@@ -171,3 +171,14 @@ def test_ensemble_standard_errors(orc):
     # a single realization has no standard error
     one = orc.ensemble_stats(lv, H, mbar[:1])
     assert math.isnan(one["S_se"]) and math.isnan(one["Hc_se"])
+
+
+def test_oracle_threads_do_not_change_results(orc):
+    # cell loops spread over threads when there are fewer realizations than
+    # threads: every cell is still computed the same way
+    lv = _cone_level((0, 0, 1), dims=(64, 32, 40))
+    a, fa = orc.run_batch(lv, [1, 2], 20, threads=1, want_final=True)
+    b, fb = orc.run_batch(lv, [1, 2], 20, threads=4, want_final=True)
+    c, fc = orc.run_batch(lv, [1, 2], 20, threads=2, want_final=True)
+    assert np.array_equal(a, b) and np.array_equal(fa, fb)
+    assert np.array_equal(a, c) and np.array_equal(fa, fc)
