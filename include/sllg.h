@@ -25,7 +25,8 @@
  *     The library never allocates or frees device memory.
  *   - Work is enqueued on the caller's HIP stream (hipStream_t passed as
  *     void*; NULL = the default stream).  sllg_run_* return without waiting;
- *     sllg_loop, sllg_grad and sllg_get_state synchronise that stream.
+ *     sllg_sync, sllg_loop, sllg_grad and sllg_get_state synchronise that
+ *     stream and report failures of the kernels enqueued before them.
  *   - Host arrays are owned by the caller.  A context is not thread safe.
  *   - SI units inside; fields in the loop outputs are in Oe.
  */
@@ -45,8 +46,22 @@ enum {
     SLLG_E_WORKSPACE = -2,  /* workspace missing, misaligned or too small                   */
     SLLG_E_CAPACITY = -3,   /* host output array too small; *n_out holds the size needed     */
     SLLG_E_STATE = -4,      /* call-order error (e.g. grad without checkpoints)              */
-    SLLG_E_HIP = -5,        /* HIP runtime error; text in sllg_last_error()                  */
-    SLLG_E_NUMERIC = -6     /* a cell's |m| became non-finite or drifted from 1              */
+    SLLG_E_HIP = -5,        /* HIP runtime error, or a slab-plan exchange wait that gave up;
+                               text in sllg_last_error()                                    */
+    SLLG_E_NUMERIC = -6     /* a loop ordinate (mean m_z of a realization) became non-finite:
+                               the magnetisation blew up (e.g. a time step far too large).
+                               |m| itself is renormalised every stage and not checked     */
+};
+
+/* Process-wide options, read by every later sllg_init (sllg_set_options). */
+enum {
+    SLLG_OPT_NO_TUNE = 1,   /* no timing at init: streamed levels keep the default tile
+                               shape and the slab plan is not tried; pin shapes afterwards
+                               with sllg_set_stream_shape / sllg_set_slab_shape           */
+    SLLG_OPT_NO_SLAB = 2,   /* init never picks the slab plan (plan 3) on its own          */
+    SLLG_OPT_NO_GRAPH = 4,  /* streamed steps are launched one by one, not replayed from
+                               HIP graphs of 128 launches                                   */
+    SLLG_OPT_VERBOSE = 8    /* the tuners print every candidate's time to stderr           */
 };
 
 enum { SLLG_WAVE_TRIANGLE = 0, SLLG_WAVE_COSINE = 1, SLLG_WAVE_CONSTANT = 2 };
@@ -121,13 +136,25 @@ int sllg_init(const sllg_material* mat, const sllg_level* levels, int32_t n_leve
               int32_t ckpt_every, void* d_workspace, size_t ws_bytes,
               void* hip_stream, sllg_ctx** out);
 
-/* Enqueue the remaining steps of the sweep for every level and realization. */
+/* Enqueue the remaining steps of the sweep for every level and realization.
+ * Asynchronous: failures inside kernels (the device status word: a
+ * non-finite loop ordinate, a slab exchange that timed out) are reported by
+ * the next call that synchronises (sllg_sync, sllg_loop, sllg_grad,
+ * sllg_get_state).  After an exchange timeout the remaining slab launches of
+ * the run do nothing and the state is undefined until sllg_reset. */
 int sllg_run_sweep(sllg_ctx* ctx);
 
-/* Enqueue at most nsteps further steps (levels stop at their own sweep end). */
+/* Enqueue at most nsteps further steps (levels stop at their own sweep end).
+ * Asynchronous, as sllg_run_sweep. */
 int sllg_run_steps(sllg_ctx* ctx, int64_t nsteps);
 
-/* Reset every level to step 0 (all cells +z, loops cleared). */
+/* Wait for the context's stream and report the device status word:
+ * SLLG_E_HIP if a slab exchange wait gave up, SLLG_E_NUMERIC if a loop
+ * ordinate became non-finite, else SLLG_OK. */
+int sllg_sync(sllg_ctx* ctx);
+
+/* Reset every level to step 0 (all cells +z, loops cleared, device status
+ * word cleared). */
 int sllg_reset(sllg_ctx* ctx);
 
 /* Copy one loop to the host and analyse it.  real = -1 gives the ensemble
@@ -149,6 +176,18 @@ int sllg_loop(sllg_ctx* ctx, int32_t level, int32_t real, double* H_Oe, double* 
  * that SLLG_E_INVAL.  g_hc is NaN when the mean loop has no crossing on a
  * branch.  FP64 accumulation; synchronises the stream. */
 int sllg_grad(sllg_ctx* ctx, int32_t level, double g_area[4], double g_hc[4]);
+
+/* Set the process-wide SLLG_OPT_* flags that later sllg_init calls use
+ * (existing contexts keep theirs).  SLLG_E_INVAL for unknown bits. */
+int sllg_set_options(int32_t flags);
+
+/* Polls of one exchange word a slab-plan workgroup makes before it gives up
+ * (default 2^20, each poll followed by a short sleep).  A wait that gives up
+ * sets the status word, ends every workgroup of the launch and makes the
+ * following slab launches return at once; sllg_sync then reports SLLG_E_HIP.
+ * 0 makes every wait that does not find its words at the first poll give up
+ * (for testing the error path; every kernel still exits normally). */
+int sllg_set_spin_limit(sllg_ctx* ctx, uint32_t polls);
 
 /* Thread-local text of the last error. */
 const char* sllg_last_error(void);

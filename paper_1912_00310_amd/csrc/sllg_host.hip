@@ -264,6 +264,9 @@ struct sllg_ctx {
     // HIP graphs of kGraphSteps stream launches per level (the stream kernel
     // reads its step index from device memory, so one graph serves any step)
     bool use_graph = true;
+    // polls of one exchange word before a slab workgroup gives up (bounded
+    // waits; sllg_set_spin_limit)
+    uint32_t spin_limit = 1u << 20;
     hipStream_t cap_stream = nullptr;
     std::map<int, hipGraphExec_t> graphs;
 };
@@ -289,9 +292,9 @@ int validate(const sllg_material* m, const sllg_level* L, int n)
         return fail(SLLG_E_INVAL, "alpha_ref must be >= 0");
     for (int i = 0; i < n; ++i) {
         const sllg_level& l = L[i];
-        if (l.nx < 1 || l.ny < 1 || l.nz < 1 || l.nx > 1023 || l.ny > 1023 || l.nz > 1023 ||
+        if (l.nx < 1 || l.ny < 1 || l.nz < 1 || l.nx > 4096 || l.ny > 4096 || l.nz > 4096 ||
             (int64_t)l.nx * l.ny * l.nz > (1 << 26))
-            return fail(SLLG_E_INVAL, "level %d: dims must be 1..1023 and at most 2^26 cells", i);
+            return fail(SLLG_E_INVAL, "level %d: dims must be 1..4096 and at most 2^26 cells", i);
         if (!(l.b >= 1.0)) return fail(SLLG_E_INVAL, "level %d: b must be >= 1", i);
         if (l.n_real < 1) return fail(SLLG_E_INVAL, "level %d: n_real must be >= 1", i);
         if (!(l.alpha >= 0) && !(m->sr_ref_Oe_per_ns > 0))
@@ -962,8 +965,9 @@ hipError_t launch_slab_t(sllg_ctx* C, int level, int64_t n0, int ns, bool check_
     float* ckpt = C->d_ckpt;
     int ck = C->ckpt_every;
     int* status = C->d_status;
+    uint32_t spin = C->spin_limit;
     void* args[] = {&slabs, &insts, &levels, &b0, &b1, &axes, &xch, &tag_base, &part, &pstride, &ckpt, &ck,
-                    &n0, &ns, &status};
+                    &n0, &ns, &status, &spin};
     return hipLaunchCooperativeKernel(fn, dim3((unsigned)h.nslab), dim3(NT), args, (unsigned)lds, C->stream);
 }
 
@@ -1171,6 +1175,9 @@ int reset_state(sllg_ctx* C)
     return SLLG_OK;
 }
 
+// Process-wide options read by sllg_init (sllg_set_options).
+int g_options = 0;
+
 // Timing-based choice of the stream tile shape (a few steps per candidate),
 // cached per (dims, instances, device) for the process.
 std::map<std::tuple<int, int, int, int>, std::pair<int, int>> g_tuned;
@@ -1188,17 +1195,6 @@ int tune_stream(sllg_ctx* C, int level)
         return SLLG_OK;
     }
     default_stream_shape(C, h);
-    // SLLG_STREAM_SHAPE="shape,tz" pins the tile shape (experiments)
-    if (const char* f = getenv("SLLG_STREAM_SHAPE")) {
-        int sh = -1, tz = -1;
-        if (sscanf(f, "%d,%d", &sh, &tz) == 2 && sh >= 0 && sh < kNumShapes && tz >= 1 &&
-            shape_fits(h.in, kShapes[sh]) && tiles_for(h.in, kShapes[sh], tz) * h.ninst <= C->lay.max_tiles) {
-            h.shape = sh;
-            h.tz = tz;
-            g_tuned[key] = {sh, tz};
-            return SLLG_OK;
-        }
-    }
     std::vector<std::pair<int, int>> cands;
     for (int s = 0; s < kNumShapes; ++s) {
         const Shape& S = kShapes[s];
@@ -1262,7 +1258,7 @@ int tune_stream(sllg_ctx* C, int level)
             HIP_OK(hipEventElapsedTime(&t, e0, e1));
             ms = std::min(ms, t);
         }
-        if (getenv("SLLG_TUNE_VERBOSE"))
+        if (g_options & SLLG_OPT_VERBOSE)
             fprintf(stderr, "tune level %d: shape %d (%d,%d,%d,%d) tz %d tiles %d: %.2f us/step\n", level,
                     c.first, kShapes[c.first].kind, kShapes[c.first].tx, kShapes[c.first].ty,
                     kShapes[c.first].pz, c.second, h.ntiles, 1000.0 * ms / reps);
@@ -1298,27 +1294,6 @@ int tune_slab(sllg_ctx* C, int level, double* best_ms)
     }
     const int P = h.in.nx * h.in.ny;
     const int saved_plan = h.plan;
-    // SLLG_SLAB_SHAPE="kernel,tz" pins the slab kernel and thickness (profiling)
-    if (const char* f = getenv("SLLG_SLAB_SHAPE")) {
-        int ki = -1, tz = -1;
-        if (sscanf(f, "%d,%d", &ki, &tz) == 2 && ki >= 0 && ki < kNumSlabKernels && tz >= 1 && tz <= h.in.nz) {
-            h.plan = kPlanSlab;
-            h.slab_kernel = ki;
-            h.slab_tz = tz;
-            int rc = replan(C);
-            if (rc) return rc;
-            bool fits = false;
-            if (dispatch_slab(C, level, 0, 1, true, &fits) == hipSuccess && fits) {
-                g_tuned_slab[key] = std::make_tuple(ki, tz, 0.0);
-                *best_ms = 0.0;
-                h.plan = saved_plan;
-                return replan(C);
-            }
-            h.plan = saved_plan;
-            int rc2 = replan(C);
-            if (rc2) return rc2;
-        }
-    }
     const int tzs[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 14, 16, 20, 24, 28, 32};
     hipEvent_t e0, e1;
     HIP_OK(hipEventCreate(&e0));
@@ -1355,7 +1330,19 @@ int tune_slab(sllg_ctx* C, int level, double* best_ms)
                 HIP_OK(hipEventElapsedTime(&t, e0, e1));
                 ms = std::min(ms, t);
             }
-            if (getenv("SLLG_TUNE_VERBOSE"))
+            // a candidate whose bounded waits gave up is dropped (its time
+            // means nothing) and the status word cleared for the next one
+            int st[4] = {0, 0, 0, 0};
+            HIP_OK(hipMemcpyAsync(st, C->d_status, sizeof(st), hipMemcpyDeviceToHost, C->stream));
+            HIP_OK(hipStreamSynchronize(C->stream));
+            if (st[0] & 2) {
+                HIP_OK(hipMemsetAsync(C->d_status, 0, sizeof(int) * 4, C->stream));
+                if (g_options & SLLG_OPT_VERBOSE)
+                    fprintf(stderr, "tune level %d: slab kernel %d tz %d dropped (exchange timed out)\n", level,
+                            ki, tz);
+                continue;
+            }
+            if (g_options & SLLG_OPT_VERBOSE)
                 fprintf(stderr, "tune level %d: slab kernel %d (%d,%d) tz %d slabs %d: %.3f us/step\n", level, ki,
                         kSlabKernels[ki].nt, kSlabKernels[ki].k, tz, h.nslab, 1000.0 * ms / kTuneSteps);
             if (ms / kTuneSteps < *best_ms) {
@@ -1377,9 +1364,6 @@ int tune_slab(sllg_ctx* C, int level, double* best_ms)
     int rc = replan(C);
     if (rc) return rc;
     HIP_OK(hipStreamSynchronize(C->stream));
-    int st[4] = {0, 0, 0, 0};
-    HIP_OK(hipMemcpy(st, C->d_status, sizeof(st), hipMemcpyDeviceToHost));
-    if (st[0] & 2) return fail(SLLG_E_HIP, "slab exchange timed out while tuning");
     return SLLG_OK;
 }
 
@@ -1431,12 +1415,17 @@ double wave_host(const LevelHost& h, int wave, int64_t n)
     return 1.0;
 }
 
+// Device status word: bit 0 (value 1) a non-finite loop ordinate, bit 1
+// (value 2) a slab exchange wait that gave up.  Synchronises the stream.
 int check_status(sllg_ctx* C)
 {
     int st[4] = {0, 0, 0, 0};
     HIP_OK(hipMemcpyAsync(st, C->d_status, sizeof(st), hipMemcpyDeviceToHost, C->stream));
     HIP_OK(hipStreamSynchronize(C->stream));
-    if (st[0]) return fail(SLLG_E_NUMERIC, "non-finite magnetisation in a loop (status %d)", st[0]);
+    if (st[0] & 2)
+        return fail(SLLG_E_HIP, "slab exchange timed out (a neighbour's boundary words did not arrive); "
+                                "the state is undefined until sllg_reset");
+    if (st[0] & 1) return fail(SLLG_E_NUMERIC, "non-finite loop ordinate (the magnetisation blew up)");
     return SLLG_OK;
 }
 
@@ -1448,6 +1437,27 @@ int check_status(sllg_ctx* C)
 extern "C" {
 
 const char* sllg_last_error(void) { return g_err.c_str(); }
+
+int sllg_set_options(int32_t flags)
+{
+    if (flags & ~(SLLG_OPT_NO_TUNE | SLLG_OPT_NO_SLAB | SLLG_OPT_NO_GRAPH | SLLG_OPT_VERBOSE))
+        return fail(SLLG_E_INVAL, "unknown option bits 0x%x", flags);
+    g_options = flags;
+    return SLLG_OK;
+}
+
+int sllg_set_spin_limit(sllg_ctx* C, uint32_t polls)
+{
+    if (!C) return fail(SLLG_E_INVAL, "null context");
+    C->spin_limit = polls;
+    return SLLG_OK;
+}
+
+int sllg_sync(sllg_ctx* C)
+{
+    if (!C) return fail(SLLG_E_INVAL, "null context");
+    return check_status(C);
+}
 
 size_t sllg_workspace_bytes(const sllg_material* mat, const sllg_level* levels, int32_t n_levels,
                             int32_t ckpt_every)
@@ -1546,7 +1556,7 @@ int sllg_init(const sllg_material* mat, const sllg_level* levels, int32_t n_leve
         C->max_lds = (int)std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
         C->num_cus = prop.multiProcessorCount;
     }
-    C->use_graph = !(getenv("SLLG_GRAPH") && getenv("SLLG_GRAPH")[0] == '0');
+    C->use_graph = !(g_options & SLLG_OPT_NO_GRAPH);
     C->h_levels.resize(n_levels);
     for (int i = 0; i < n_levels; ++i) {
         LevelHost& h = C->lv[i];
@@ -1599,7 +1609,7 @@ int sllg_init(const sllg_material* mat, const sllg_level* levels, int32_t n_leve
     // tune stream shapes on first use of a shape, then start from step 0 again
     bool tuned = false;
     for (int i = 0; i < n_levels; ++i)
-        if (C->lv[i].plan == kPlanStream && !getenv("SLLG_NO_TUNE")) {
+        if (C->lv[i].plan == kPlanStream && !(g_options & SLLG_OPT_NO_TUNE)) {
             rc = tune_stream(C, i);
             if (rc) {
                 delete C;
@@ -1609,7 +1619,8 @@ int sllg_init(const sllg_material* mat, const sllg_level* levels, int32_t n_leve
         }
     for (int i = 0; i < n_levels; ++i) {
         LevelHost& h = C->lv[i];
-        if (h.plan != kPlanStream || !slab_eligible(h.in) || getenv("SLLG_NO_SLAB")) continue;
+        if (h.plan != kPlanStream || !slab_eligible(h.in) || (g_options & (SLLG_OPT_NO_SLAB | SLLG_OPT_NO_TUNE)))
+            continue;
         double slab_ms = 1e30;
         rc = tune_slab(C, i, &slab_ms);
         if (rc) {
@@ -1781,8 +1792,7 @@ int sllg_get_state(sllg_ctx* C, int32_t level, int32_t real, float* host_m)
     const InstDev& I = C->h_insts[h.inst0 + real];
     const float* src = ((h.step & 1) ? C->d_buf1 : C->d_buf0) + I.state_off;
     HIP_OK(hipMemcpyAsync(host_m, src, sizeof(float) * 3 * h.ncell, hipMemcpyDeviceToHost, C->stream));
-    HIP_OK(hipStreamSynchronize(C->stream));
-    return SLLG_OK;
+    return check_status(C);
 }
 
 int sllg_set_state(sllg_ctx* C, int32_t level, int32_t real, const float* host_m)

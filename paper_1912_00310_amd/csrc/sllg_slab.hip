@@ -38,7 +38,6 @@ struct SlabDev {
     int32_t pad0, pad1;
 };
 
-constexpr uint32_t kSlabSpinLimit = 1u << 20;
 constexpr uint32_t kTagBit = 1u << 30;
 
 // 32-bit exchange word: the FP32 pattern of |v| < 2 with bit 30 as the tag;
@@ -80,7 +79,8 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
                                              float* __restrict__ buf1, const float* __restrict__ axes,
                                              uint64_t* __restrict__ xch64, uint32_t tag_base,
                                              double* __restrict__ partials, int pstride, float* __restrict__ ckpt,
-                                             int ckpt_every, int64_t n0, int nsteps, int* __restrict__ status)
+                                             int ckpt_every, int64_t n0, int nsteps, int* __restrict__ status,
+                                             uint32_t spin_limit)
 {
     extern __shared__ float4 lds_slab[];
     __shared__ double red[NT / 64];
@@ -118,7 +118,9 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
         return xch_par[par] + (static_cast<int64_t>(slab) * 4 + slot) * 3 * P;
     };
     const int nzs_prev = S.prev >= 0 ? slabs[S.prev].nzs : 0;
-    if (tid == 0) s_abort = 0;
+    // a launch after an exchange timeout (status bit 2) does nothing: the
+    // state is undefined until the host resets it
+    if (tid == 0) s_abort = (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2) ? 1 : 0;
 
     for (int st = tid; st <= nsteps; st += NT) s_hz[st] = static_cast<float>(L.hz_amp * wave_at(L, n0 + st));
     // ---- load m_n of planes z0-2 .. z0+nzs+1 (those inside the grid)
@@ -132,6 +134,7 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
         }
     }
     __syncthreads();
+    if (s_abort) return;
 
     const bool axes_on = L.has_axes != 0;
     // step constants in vector registers with one plane per thread (a scalar
@@ -244,7 +247,7 @@ __global__ __launch_bounds__(NT) void k_slab(const SlabDev* __restrict__ slabs, 
                 w1 = ld_word32(s + P + c);
                 w2 = ld_word32(s + 2 * P + c);
                 if ((w0 & kTagBit) == want && (w1 & kTagBit) == want && (w2 & kTagBit) == want) break;
-                if (++spins > kSlabSpinLimit) {
+                if (++spins > spin_limit) {
                     ok = false;
                     break;
                 }
@@ -292,7 +295,8 @@ __global__ __launch_bounds__(NT) void k_slab2(const SlabDev* __restrict__ slabs,
                                               float* __restrict__ buf1, const float* __restrict__ axes,
                                               uint64_t* __restrict__ xch, uint32_t tag_base,
                                               double* __restrict__ partials, int pstride, float* __restrict__ ckpt,
-                                              int ckpt_every, int64_t n0, int nsteps, int* __restrict__ status)
+                                              int ckpt_every, int64_t n0, int nsteps, int* __restrict__ status,
+                                             uint32_t spin_limit)
 {
     extern __shared__ float lds[];
     __shared__ double red[NT / 64];
@@ -321,7 +325,9 @@ __global__ __launch_bounds__(NT) void k_slab2(const SlabDev* __restrict__ slabs,
     };
     // rows that poll the halo below (h = 0) and above (h = 1)
     const int prow0 = nzs % NPP, prow1 = (nzs + 1) % NPP;
-    if (tid == 0) s_abort = 0;
+    // a launch after an exchange timeout (status bit 2) does nothing: the
+    // state is undefined until the host resets it
+    if (tid == 0) s_abort = (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2) ? 1 : 0;
 
     {
         const float* mi = ((n0 & 1) ? buf1 : buf0) + I.state_off;
@@ -335,6 +341,7 @@ __global__ __launch_bounds__(NT) void k_slab2(const SlabDev* __restrict__ slabs,
         }
     }
     __syncthreads();
+    if (s_abort) return;
 
     const bool axes_on = L.has_axes != 0;
     const float* ax = axes + L.axes_off;
@@ -359,7 +366,7 @@ __global__ __launch_bounds__(NT) void k_slab2(const SlabDev* __restrict__ slabs,
             w1 = ld_word(src + P + c);
             w2 = ld_word(src + 2 * P + c);
             if (word_tag(w0) == tag && word_tag(w1) == tag && word_tag(w2) == tag) break;
-            if (++spins > kSlabSpinLimit) return false;
+            if (++spins > spin_limit) return false;
             __builtin_amdgcn_s_sleep(1);
         }
         dst[c] = word_val(w0);

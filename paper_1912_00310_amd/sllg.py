@@ -20,6 +20,7 @@ ERRORS = {-1: "SLLG_E_INVAL", -2: "SLLG_E_WORKSPACE", -3: "SLLG_E_CAPACITY",
           -4: "SLLG_E_STATE", -5: "SLLG_E_HIP", -6: "SLLG_E_NUMERIC"}
 WAVES = {"triangle": 0, "cosine": 1, "constant": 2}
 PLAN_AUTO, PLAN_RESIDENT, PLAN_STREAM, PLAN_SLAB = 0, 1, 2, 3
+OPT_NO_TUNE, OPT_NO_SLAB, OPT_NO_GRAPH, OPT_VERBOSE = 1, 2, 4, 8
 
 
 class SllgError(RuntimeError):
@@ -96,6 +97,9 @@ def lib():
             "sllg_get_axes": (C.c_int, [vp, C.c_int32, P(C.c_float)]),
             "sllg_set_timing": (C.c_int, [vp, C.c_int32]),
             "sllg_kernel_time": (C.c_int, [vp, P(C.c_double), P(C.c_int64), P(C.c_int64)]),
+            "sllg_sync": (C.c_int, [vp]),
+            "sllg_set_options": (C.c_int, [C.c_int32]),
+            "sllg_set_spin_limit": (C.c_int, [vp, C.c_uint32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -112,7 +116,8 @@ def exported_symbols():
         "sllg_loop", "sllg_grad", "sllg_last_error", "sllg_free", "sllg_level_params",
         "sllg_level_step", "sllg_level_kernel", "sllg_get_state", "sllg_set_state", "sllg_set_plan",
         "sllg_set_slab_shape", "sllg_set_stream_shape",
-        "sllg_philox_probe", "sllg_get_axes", "sllg_set_timing", "sllg_kernel_time")]
+        "sllg_philox_probe", "sllg_get_axes", "sllg_set_timing", "sllg_kernel_time",
+        "sllg_sync", "sllg_set_options", "sllg_set_spin_limit")]
 
 
 def _check(fn, rc):
@@ -200,7 +205,12 @@ class Sim:
         _check("sllg_reset", lib().sllg_reset(self.ctx))
 
     def synchronize(self):
-        self.stream.synchronize()
+        """Wait for the stream and raise if a kernel reported a failure."""
+        _check("sllg_sync", lib().sllg_sync(self.ctx))
+
+    def set_spin_limit(self, polls: int):
+        """Polls of one slab exchange word before the wait gives up."""
+        _check("sllg_set_spin_limit", lib().sllg_set_spin_limit(self.ctx, int(polls)))
 
     # -- results -------------------------------------------------------------
     def loop(self, level: int = 0, real: int = -1):
@@ -283,6 +293,11 @@ class Sim:
         cells = C.c_int64()
         _check("sllg_kernel_time", lib().sllg_kernel_time(self.ctx, C.byref(ms), C.byref(nl), C.byref(cells)))
         return ms.value, nl.value, cells.value
+
+
+def set_options(flags: int):
+    """Process-wide OPT_* flags for contexts created afterwards."""
+    _check("sllg_set_options", lib().sllg_set_options(int(flags)))
 
 
 def philox_probe(seed, level, tag, cells, steps, device="cuda:0"):

@@ -1,0 +1,133 @@
+"""GPU parity at the stated tolerance on every workload, in the launch
+configuration the benchmark uses (the tuned plan of a fresh context):
+every m component within 1e-5 of the FP64 oracle over the first 1000 Heun
+steps, the loop ordinates within 2e-6.
+
+  * 8x24x56 rod, b = 1, all 8 realizations (slab plan), 1000 steps;
+  * the four-level batch (1024 instances, the b = 1 level streamed, the
+    others resident), 1000 steps, four realizations of every level compared;
+  * the 128x128x512 block at full size, 20 steps over all 8.4M cells (the
+    oracle takes about a second per step), and a 128x128x24 slice of it for
+    1000 steps on the tile kernel the benchmark's tuner picks for the block;
+  * the 64-realization adjoint workload (2x6x14, b = 4), 1000 steps of all 64.
+
+The oracle runs of independent realizations go to a thread pool (the C
+oracle releases the GIL).
+"""
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import sllg_workloads as W
+from oracle import gk
+
+pytestmark = pytest.mark.gpu
+
+TOL_M = 1e-5
+TOL_MBAR = 2e-6
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1912_00310_amd as P
+    P.lib()
+    return P
+
+
+def _pool_run(orc, jobs):
+    """jobs: list of (lv, seed, n0, nsteps, m, u) -> list of (m, mbar)."""
+    with ThreadPoolExecutor(max_workers=min(16, max(1, len(jobs)))) as ex:
+        return list(ex.map(lambda j: orc.run(*j[:5], u=j[5]), jobs))
+
+
+def _compare_levels(P, orc, wl, reals, nsteps=1000, every=250, sim=None):
+    """Step a fresh context of the workload (tuned plan) nsteps, comparing the
+    listed realizations of every level with the oracle every `every` steps."""
+    levels = wl["levels"]
+    own = sim is None
+    if own:
+        sim = P.Sim(wl["material"], levels)
+    lvs = [gk.compile_level(wl["material"], lvd, l) for l, lvd in enumerate(levels)]
+    us = [orc.make_axes(lv) for lv in lvs]
+    state = {}
+    mbars = {}
+    for l, lv in enumerate(lvs):
+        N = lv["nx"] * lv["ny"] * lv["nz"]
+        for r in reals[l]:
+            state[(l, r)] = np.tile([0.0, 0.0, 1.0], (N, 1))
+            mbars[(l, r)] = [1.0]
+    worst = 0.0
+    n = 0
+    while n < nsteps:
+        k = min(every, nsteps - n)
+        sim.run_steps(k)
+        keys = list(state)
+        out = _pool_run(orc, [(lvs[l], levels[l]["seed_base"] + r, n, k, state[(l, r)], us[l]) for l, r in keys])
+        n += k
+        for (l, r), (m_ref, mb) in zip(keys, out):
+            state[(l, r)] = m_ref
+            mbars[(l, r)].extend(mb[1:].tolist())
+            d = float(np.abs(sim.get_state(l, r).T.astype(np.float64) - m_ref).max())
+            worst = max(worst, d)
+            assert d <= TOL_M, (l, r, n, d, sim.kernel_name(l))
+    for (l, r), mb in mbars.items():
+        _, mh, _ = sim.loop(l, r)
+        rec = levels[l].get("record_every", 1)
+        ref = np.array(mb)[::rec]
+        assert np.abs(mh - ref[:len(mh)]).max() <= TOL_MBAR, (l, r)
+    kernels = [sim.kernel_name(l) for l in range(len(levels))]
+    if own:
+        sim.close()
+    return worst, kernels
+
+
+def test_rod_b1_all_8_realizations_1000_steps(P, orc):
+    wl = W.workload("rod_b1_ens8")
+    worst, kernels = _compare_levels(P, orc, wl, [range(8)])
+    print(f"rod b=1 x8, 1000 steps on {kernels[0]}: worst |dm| = {worst:.2e}")
+    assert kernels[0].startswith("k_slab"), kernels
+
+
+def test_multilevel_batch_1000_steps(P, orc):
+    wl = W.workload("multilevel_ens256")
+    reals = [(0, 1, 128, 255)] * 4
+    worst, kernels = _compare_levels(P, orc, wl, reals)
+    print(f"four-level batch, 1000 steps on {kernels}: worst |dm| = {worst:.2e}")
+
+
+def test_adjoint_workload_all_64_realizations_1000_steps(P, orc):
+    wl = W.workload("rod_b4_adjoint64")
+    worst, kernels = _compare_levels(P, orc, wl, [range(64)], every=500)
+    print(f"2x6x14 x64, 1000 steps on {kernels}: worst |dm| = {worst:.2e}")
+
+
+def test_block_full_size_20_steps(P, orc):
+    # all 8.4M cells of the block on the tuned tile kernel, 20 steps
+    wl = W.workload("block_b2_cone10")
+    worst, kernels = _compare_levels(P, orc, wl, [(0,)], nsteps=20, every=10)
+    print(f"block 128x128x512, 20 steps on {kernels[0]}: worst |dm| = {worst:.2e}")
+
+
+def test_block_slice_1000_steps_bench_tile_kernel(P, orc):
+    # a 128x128x24 slice for 1000 steps on the tile kernel the tuner picks
+    # for the full block (same x-y tiling; the z depth of a tile is cut to the
+    # slice)
+    import re
+    full = W.workload("block_b2_cone10")
+    sim = P.Sim(full["material"], full["levels"])
+    name = sim.kernel_name(0)
+    sim.close()
+    mt = re.match(r"k_rows2<(\d+),(\d+)> tz (\d+)", name)
+    assert mt, name
+    nt, cpt, tz = (int(x) for x in mt.groups())
+    wl = W.workload("block_b2_cone10")
+    wl["levels"][0]["nz"] = 24
+    sim = P.Sim(wl["material"], wl["levels"])
+    sim.set_stream_shape(0, 2, nt, cpt, 1, min(tz, 12))
+    worst, kernels = _compare_levels(P, orc, wl, [(0,)], nsteps=1000, every=250, sim=sim)
+    sim.close()
+    print(f"block slice 128x128x24, 1000 steps on {kernels[0]} (full block: {name}): worst |dm| = {worst:.2e}")

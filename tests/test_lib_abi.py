@@ -91,3 +91,11 @@ def test_null_context_calls(L):
     assert lib.sllg_run_steps(None, 1) == -1
     assert lib.sllg_level_step(None, 0) == -1
     lib.sllg_free(None)
+
+
+def test_options_and_null_contexts_rejected(L):
+    lib = L.lib()
+    assert lib.sllg_set_options(16) == -1
+    assert lib.sllg_set_options(0) == 0
+    assert lib.sllg_sync(None) == -1
+    assert lib.sllg_set_spin_limit(None, 0) == -1
