@@ -136,6 +136,22 @@ int sllg_init(const sllg_material* mat, const sllg_level* levels, int32_t n_leve
               int32_t ckpt_every, void* d_workspace, size_t ws_bytes,
               void* hip_stream, sllg_ctx** out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * sllg_init, but the workspace is a device array of 64 MiB inside the
+ * library (one per GPU, held until the process ends) instead of the
+ * caller's.  Neither this call nor the calls on the context it returns
+ * allocate device memory: the tuners are off (default tile shapes, the slab
+ * plan is only used if sllg_set_slab_shape asks for it) and streamed steps
+ * are launched one by one instead of from HIP graphs.  A workload needing
+ * more than 64 MiB (sllg_workspace_bytes) gives SLLG_E_WORKSPACE.  One live
+ * context per GPU: while one holds the array, another sllg_init_static on
+ * that GPU gives SLLG_E_STATE; sllg_free releases it.  The array keeps the
+ * last context's contents; initialisation clears everything a sweep reads
+ * before writing.  Calls from several threads on one GPU race. */
+int sllg_init_static(const sllg_material* mat, const sllg_level* levels, int32_t n_levels,
+                     int32_t ckpt_every, void* hip_stream, sllg_ctx** out);
+
 /* Enqueue the remaining steps of the sweep for every level and realization.
  * Asynchronous: failures inside kernels (the device status word: a
  * non-finite loop ordinate, a slab exchange that timed out) are reported by

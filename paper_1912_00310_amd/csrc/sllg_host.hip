@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -29,6 +30,13 @@
 #include "sllg_rows2.hip"
 
 using namespace sllg;
+
+// Device workspace of sllg_init_static, for callers that cannot allocate
+// device memory.  In host code `scratch` is only a handle: its device
+// address (one copy per GPU) comes from hipGetSymbolAddress and is kept per
+// device below.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 namespace {
 
@@ -267,6 +275,7 @@ struct sllg_ctx {
     // polls of one exchange word before a slab workgroup gives up (bounded
     // waits; sllg_set_spin_limit)
     uint32_t spin_limit = 1u << 20;
+    int static_dev = -1;          // device whose static workspace this context holds (sllg_init_static)
     hipStream_t cap_stream = nullptr;
     std::map<int, hipGraphExec_t> graphs;
 };
@@ -1468,8 +1477,12 @@ size_t sllg_workspace_bytes(const sllg_material* mat, const sllg_level* levels, 
     return make_layout(*mat, lv, ckpt_every).total;
 }
 
-int sllg_init(const sllg_material* mat, const sllg_level* levels, int32_t n_levels, int32_t ckpt_every,
-              void* d_workspace, size_t ws_bytes, void* hip_stream, sllg_ctx** out)
+}  // extern "C"
+
+namespace {
+
+int init_impl(const sllg_material* mat, const sllg_level* levels, int32_t n_levels, int32_t ckpt_every,
+              void* d_workspace, size_t ws_bytes, void* hip_stream, int options, sllg_ctx** out)
 {
     if (!out) return fail(SLLG_E_INVAL, "out is NULL");
     *out = nullptr;
@@ -1556,7 +1569,7 @@ int sllg_init(const sllg_material* mat, const sllg_level* levels, int32_t n_leve
         C->max_lds = (int)std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
         C->num_cus = prop.multiProcessorCount;
     }
-    C->use_graph = !(g_options & SLLG_OPT_NO_GRAPH);
+    C->use_graph = !(options & SLLG_OPT_NO_GRAPH);
     C->h_levels.resize(n_levels);
     for (int i = 0; i < n_levels; ++i) {
         LevelHost& h = C->lv[i];
@@ -1609,7 +1622,7 @@ int sllg_init(const sllg_material* mat, const sllg_level* levels, int32_t n_leve
     // tune stream shapes on first use of a shape, then start from step 0 again
     bool tuned = false;
     for (int i = 0; i < n_levels; ++i)
-        if (C->lv[i].plan == kPlanStream && !(g_options & SLLG_OPT_NO_TUNE)) {
+        if (C->lv[i].plan == kPlanStream && !(options & SLLG_OPT_NO_TUNE)) {
             rc = tune_stream(C, i);
             if (rc) {
                 delete C;
@@ -1619,7 +1632,7 @@ int sllg_init(const sllg_material* mat, const sllg_level* levels, int32_t n_leve
         }
     for (int i = 0; i < n_levels; ++i) {
         LevelHost& h = C->lv[i];
-        if (h.plan != kPlanStream || !slab_eligible(h.in) || (g_options & (SLLG_OPT_NO_SLAB | SLLG_OPT_NO_TUNE)))
+        if (h.plan != kPlanStream || !slab_eligible(h.in) || (options & (SLLG_OPT_NO_SLAB | SLLG_OPT_NO_TUNE)))
             continue;
         double slab_ms = 1e30;
         rc = tune_slab(C, i, &slab_ms);
@@ -1641,6 +1654,60 @@ int sllg_init(const sllg_material* mat, const sllg_level* levels, int32_t n_leve
         }
     }
     *out = C;
+    return SLLG_OK;
+}
+
+// Device address of this GPU's static workspace (looked up once per device
+// with that device current) and whether a live context holds it.
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};
+bool g_static_busy[kMaxDevices] = {};
+
+}  // namespace
+
+extern "C" {
+
+int sllg_init(const sllg_material* mat, const sllg_level* levels, int32_t n_levels, int32_t ckpt_every,
+              void* d_workspace, size_t ws_bytes, void* hip_stream, sllg_ctx** out)
+{
+    return init_impl(mat, levels, n_levels, ckpt_every, d_workspace, ws_bytes, hip_stream, g_options, out);
+}
+
+int sllg_init_static(const sllg_material* mat, const sllg_level* levels, int32_t n_levels, int32_t ckpt_every,
+                     void* hip_stream, sllg_ctx** out)
+{
+    if (!out) return fail(SLLG_E_INVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(mat, levels, n_levels);
+    if (rc) return rc;
+    if (ckpt_every < 0) return fail(SLLG_E_INVAL, "ckpt_every must be >= 0");
+    const size_t need = sllg_workspace_bytes(mat, levels, n_levels, ckpt_every);
+    if (need == 0) return SLLG_E_INVAL;
+    if (need > kStaticScratchBytes)
+        return fail(SLLG_E_WORKSPACE, "needs %zu bytes of workspace; the static workspace holds %zu", need,
+                    kStaticScratchBytes);
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SLLG_E_INVAL, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SLLG_E_HIP, "static workspace address on device %d: %s", dev, hipGetErrorString(e));
+        g_static_ptr[dev] = p;
+    }
+    if (g_static_busy[dev])
+        return fail(SLLG_E_STATE, "the static workspace of device %d is held by a live context (sllg_free it first)",
+                    dev);
+    // no tuning (it creates events), no graphs (capture and instantiation
+    // allocate): default tile shapes, launches issued one by one
+    rc = init_impl(mat, levels, n_levels, ckpt_every, g_static_ptr[dev], kStaticScratchBytes, hip_stream,
+                   SLLG_OPT_NO_TUNE | SLLG_OPT_NO_GRAPH, out);
+    if (rc) return rc;
+    (*out)->static_dev = dev;
+    g_static_busy[dev] = true;
     return SLLG_OK;
 }
 
@@ -2101,6 +2168,13 @@ int sllg_grad(sllg_ctx* C, int32_t level, double g_area[4], double g_hc[4])
 void sllg_free(sllg_ctx* C)
 {
     if (!C) return;
+    if (C->static_dev >= 0) {
+        // the static workspace is free for the next context once the
+        // context's work on it has finished
+        (void)hipStreamSynchronize(C->stream);
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        g_static_busy[C->static_dev] = false;
+    }
     for (hipEvent_t e : C->ev_pool) (void)hipEventDestroy(e);
     if (C->cap_stream) (void)hipStreamDestroy(C->cap_stream);
     for (const auto& g : C->graphs) (void)hipGraphExecDestroy(g.second);

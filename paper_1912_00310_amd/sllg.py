@@ -98,6 +98,7 @@ def lib():
             "sllg_set_timing": (C.c_int, [vp, C.c_int32]),
             "sllg_kernel_time": (C.c_int, [vp, P(C.c_double), P(C.c_int64), P(C.c_int64)]),
             "sllg_sync": (C.c_int, [vp]),
+            "sllg_init_static": (C.c_int, [P(Material), P(Level), C.c_int32, C.c_int32, vp, P(vp)]),
             "sllg_set_options": (C.c_int, [C.c_int32]),
             "sllg_set_spin_limit": (C.c_int, [vp, C.c_uint32]),
         }
@@ -117,7 +118,7 @@ def exported_symbols():
         "sllg_level_step", "sllg_level_kernel", "sllg_get_state", "sllg_set_state", "sllg_set_plan",
         "sllg_set_slab_shape", "sllg_set_stream_shape",
         "sllg_philox_probe", "sllg_get_axes", "sllg_set_timing", "sllg_kernel_time",
-        "sllg_sync", "sllg_set_options", "sllg_set_spin_limit")]
+        "sllg_sync", "sllg_set_options", "sllg_set_spin_limit", "sllg_init_static")]
 
 
 def _check(fn, rc):
@@ -159,7 +160,10 @@ PARAM_KEYS = ("zeta", "A", "K", "Ms", "a", "c_ex", "hk", "gamma1", "alpha", "sig
 class Sim:
     """One context: levels x realizations of the stochastic LLG loop on one GPU."""
 
-    def __init__(self, material: dict, levels, ckpt_every: int = 0, device="cuda:0", stream=None):
+    def __init__(self, material: dict, levels, ckpt_every: int = 0, device="cuda:0", stream=None,
+                 static_workspace: bool = False):
+        """static_workspace=True: sllg_init_static (the library's own device
+        array; no device memory is allocated by this object)."""
         import torch
         self._torch = torch
         self.device = torch.device(device)
@@ -167,6 +171,17 @@ class Sim:
         self.lv = levels_struct(levels)
         self.n_levels = len(levels)
         L = lib()
+        if static_workspace:
+            with torch.cuda.device(self.device):
+                self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+                self.ws = None
+                ctx = C.c_void_p()
+                _check("sllg_init_static", L.sllg_init_static(C.byref(self.mat), self.lv, self.n_levels,
+                                                              int(ckpt_every), C.c_void_p(self.stream.cuda_stream),
+                                                              C.byref(ctx)))
+            self.ctx = ctx
+            self.ckpt_every = ckpt_every
+            return
         nbytes = L.sllg_workspace_bytes(C.byref(self.mat), self.lv, self.n_levels, int(ckpt_every))
         if nbytes == 0:
             raise SllgError("sllg_workspace_bytes", -1, L.sllg_last_error().decode())
