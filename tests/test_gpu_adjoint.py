@@ -1,10 +1,14 @@
-"""GPU adjoint (sllg_grad) against the FP64 oracle adjoint on the same noise.
+"""GPU adjoint (sllg_grad) against the FP64 oracle adjoint on the same noise
+and against central finite differences (relative step 1e-4) of the FP64
+oracle's forward run, at 1e-3 relative.
 
-The oracle adjoint is itself pinned to central finite differences of the FP64
-forward run (tests/test_oracle_adjoint.py).  The GPU replays the FP32
-trajectory; where the trajectories agree (short sweeps) the gradients agree to
-1e-3 relative; over the full 4e4-step sweep of 64 realizations the FP32/FP64
-trajectory difference grows and the bar is 2e-2 relative.
+The oracle adjoint is itself pinned to finite differences of the FP64 forward
+run (tests/test_oracle_adjoint.py).  The GPU replays its FP32 trajectory: on
+the full 4e4-step sweep of 64 realizations the FP32 and FP64 states drift
+apart by 2e-5 at the end (the mean loop by 2e-6), and the area gradients
+differ by about 1e-4 relative.  Finite differences of the GPU's own FP32
+forward are not used at a 1e-4 step: the rounding of a perturbed FP32 run
+moves the loop area by more than the perturbation does.
 """
 import math
 import time
@@ -95,11 +99,12 @@ def test_switching_coercive_field_gradient(P, orc):
     ga, gh, st = gpu_grads(P, wl, ckpt=256)
     ra, rh, so = oracle_grads(orc, wl)
     assert np.all(np.isfinite(gh)) and np.all(np.isfinite(rh))
-    # the FP32 and FP64 loops may select neighbouring crossing steps; the
-    # gradient of the interpolated crossing is continuous across them
-    ok, r = rel_close(gh, rh, 5e-2)
+    # measured: at most 7e-4 (the alpha component of the coercive field)
+    ok, r = rel_close(gh, rh, 1e-3)
+    print("coercive field gradient, relative difference to the FP64 adjoint:", r)
     assert ok, (gh, rh, r)
-    ok, r = rel_close(ga, ra, 5e-2)
+    ok, r = rel_close(ga, ra, 1e-3)
+    print("area gradient, relative difference to the FP64 adjoint:", r)
     assert ok, (ga, ra, r)
 
 
@@ -119,8 +124,77 @@ def test_full_adjoint_workload_64_realizations(P, orc):
     print(f"forward {1e3*(t1-t0):.1f} ms, adjoint {1e3*(t2-t1):.1f} ms, ratio {(t2-t1)/(t1-t0):.2f}")
     ra, rh, so = oracle_grads(orc, wl)
     assert math.isnan(st["Hc_sim"]) and np.all(np.isnan(gh))   # this protocol never reverses
-    ok, r = rel_close(ga, ra, 2e-2)
+    ok, r = rel_close(ga, ra, 1e-3)
+    print("relative difference to the FP64 adjoint:", r)
     assert ok, (ga, ra, r)
+    assert (t2 - t1) <= 4.0 * (t1 - t0), "gradient costs more than four forward sweeps"
+
+
+def oracle_fd(orc, wl, h=1e-4, threads=0):
+    """Central finite differences (relative step h) of the FP64 oracle's
+    ensemble-mean loop area and coercive field with respect to the level's
+    simulated K, A, alpha and ms_scale.  K and A move through K0 and A0 (the
+    rule scales them linearly), alpha through the level, ms_scale through the
+    material (Ms moves; the simulated K and A do not)."""
+    lvd0 = wl["levels"][0]
+    seeds = [lvd0["seed_base"] + r for r in range(lvd0["n_real"])]
+
+    def stats(mat, lvd):
+        lv = gk.compile_level(mat, lvd, 0)
+        H = orc.field_schedule_Oe(lv)
+        mbar, _ = orc.run_batch(lv, seeds, lv["n_steps"], threads=threads)
+        st = orc.loop_stats(H, mbar.mean(axis=0))
+        return st["S"], st["Hc"], lv
+
+    lv0 = gk.compile_level(wl["material"], lvd0, 0)
+    base = {"K": lv0["K"], "A": lv0["A"], "alpha": lv0["alpha"], "ms_scale": wl["material"]["ms_scale"]}
+    gS, gH = np.zeros(4), np.zeros(4)
+    for j, name in enumerate(("K", "A", "alpha", "ms_scale")):
+        out = []
+        for sgn in (1, -1):
+            mat, lvd = dict(wl["material"]), dict(lvd0)
+            f = 1 + sgn * h
+            if name == "K":
+                mat["K0"] *= f
+            elif name == "A":
+                mat["A0"] *= f
+            elif name == "alpha":
+                lvd["alpha"] *= f
+            else:
+                mat["ms_scale"] *= f
+            out.append(stats(mat, lvd))
+        d = 2 * h * base[name]
+        gS[j] = (out[0][0] - out[1][0]) / d
+        gH[j] = (out[0][1] - out[1][1]) / d
+    return gS, gH
+
+
+def test_full_adjoint_workload_against_oracle_finite_differences(P, orc):
+    # the north-star check: the GPU gradient of the mean loop area over the
+    # full 64-realization sweep against central differences of the FP64
+    # forward at relative step 1e-4
+    wl = W.workload("rod_b4_adjoint64")
+    ga, gh, st = gpu_grads(P, wl, ckpt=wl["ckpt_every"])
+    fS, _ = oracle_fd(orc, wl)
+    ok, r = rel_close(ga, fS, 1e-3)
+    print("relative difference to finite differences:", r)
+    assert ok, (ga, fS, r)
+
+
+def test_switching_gradients_against_oracle_finite_differences(P, orc):
+    # a loop that reverses: area and coercive-field gradients against central
+    # differences of the FP64 forward
+    wl = W.workload("rod_b4_single")
+    wl["material"]["sweep_Oe_per_ns"] = 500.0
+    wl["levels"][0].update(b=8, nx=1, ny=3, nz=7, alpha=1.0, dt_s=50e-15, n_real=8)
+    ga, gh, st = gpu_grads(P, wl, ckpt=256)
+    fS, fH = oracle_fd(orc, wl)
+    rS = np.abs(ga - fS) / np.abs(fS)
+    rH = np.abs(gh - fH) / np.abs(fH)
+    print("area:", ga, fS, rS)
+    print("coercive field:", gh, fH, rH)
+    assert np.all(rS <= 1e-3), rS
+    assert np.all(rH <= 1e-3), rH
 
 
 def test_grad_requires_checkpoints_and_full_sweep(P):
