@@ -122,7 +122,7 @@ def dominant_kernel(sim, n_levels):
     """Kernel the library times (streamed if a level is streamed, else slab,
     else resident) and its family."""
     kernels = [sim.kernel_name(l) for l in range(n_levels)]
-    fam = next((f for f in ("k_stream", "k_rows", "k_slab", "k_resident")
+    fam = next((f for f in ("k_stream", "k_rows", "k_slab", "k_resident", "k_lanes")
                 if any(k.startswith(f) for k in kernels)), "none")
     if fam == "k_rows" and any(k.startswith("k_stream") for k in kernels):
         fam = "k_stream"

@@ -237,10 +237,13 @@ int sllg_set_state(sllg_ctx* ctx, int32_t level, int32_t real, const float* host
  * kernel, 2 = one fused launch per step over tiles, 3 = persistent
  * cooperative launch in which every workgroup owns a z-slab of one
  * realization for up to 1024 steps and trades boundary planes with its two
- * neighbours through device memory each step.  All plans give bit-identical
- * states.  Changing the plan is allowed between runs.  Returns SLLG_E_INVAL
- * if the plan cannot hold the level (plan 3: more slabs than can be
- * co-resident, or a slab thicker than the workgroup's LDS holds). */
+ * neighbours through device memory each step, 4 = single-cell levels only
+ * (the single-macrospin limit): one realization per lane for up to 2^20
+ * steps per launch (automatic when every level of the context is a single
+ * cell).  All plans give bit-identical states.  Changing the plan is allowed
+ * between runs.  Returns SLLG_E_INVAL if the plan cannot hold the level
+ * (plan 3: more slabs than can be co-resident, or a slab thicker than the
+ * workgroup's LDS holds; plan 4: more than one cell). */
 int sllg_set_plan(sllg_ctx* ctx, int32_t level, int32_t plan);
 
 /* Slab plan (3) with a given kernel: kind 0 recomputes the halo predictor

@@ -28,6 +28,7 @@
 #include "sllg_adjoint.hip"
 #include "sllg_slab.hip"
 #include "sllg_rows2.hip"
+#include "sllg_lanes.hip"
 
 using namespace sllg;
 
@@ -68,7 +69,7 @@ constexpr double kGammaE = 1.76e11;
 constexpr double kGamma0 = kMu0 * kGammaE;
 constexpr double kOe = 1000.0 / (4.0 * kPi);   // A/m per Oe
 
-constexpr int kPlanAuto = 0, kPlanResident = 1, kPlanStream = 2, kPlanSlab = 3;
+constexpr int kPlanAuto = 0, kPlanResident = 1, kPlanStream = 2, kPlanSlab = 3, kPlanLanes = 4;
 static_assert(kSlabChunk < 2048, "slab exchange tags hold the step of a launch in 11 bits");
 
 // Compiled FP64 constants of one level.
@@ -800,6 +801,18 @@ hipError_t dispatch_res(sllg_ctx* C, const sllg_ctx::ResSet& rs, int64_t n0, int
     }
 }
 
+// Single-cell levels [l0, l1) (consecutive, the same sweep position): one
+// lane per realization, ns steps.
+hipError_t dispatch_lanes(sllg_ctx* C, int l0, int l1, int64_t n0, int64_t ns)
+{
+    const int i0 = C->lv[l0].inst0;
+    const int ni = C->lv[l1 - 1].inst0 + C->lv[l1 - 1].ninst - i0;
+    hipLaunchKernelGGL(k_lanes, dim3((unsigned)ceil_div(ni, kLanesThreads)), dim3(kLanesThreads), 0, C->stream,
+                       C->d_insts, i0, ni, C->d_levels, C->d_buf0, C->d_buf1, C->d_axes, C->d_records, C->d_accs,
+                       C->d_ckpt, C->ckpt_every, n0, ns, C->d_status);
+    return hipGetLastError();
+}
+
 template <int TX, int TY, int PZ>
 hipError_t launch_stream_t(sllg_ctx* C, int level)
 {
@@ -1136,6 +1149,44 @@ int run_steps(sllg_ctx* C, int64_t nsteps)
             h.step += ns;
             k -= ns;
         }
+    }
+    // single-cell levels on the lanes plan: runs of consecutive levels at the
+    // same sweep position share a launch of at most 2^20 steps
+    for (int l0 = 0; l0 < (int)C->lv.size();) {
+        if (C->lv[l0].plan != kPlanLanes) {
+            ++l0;
+            continue;
+        }
+        int l1 = l0 + 1;
+        while (l1 < (int)C->lv.size() && C->lv[l1].plan == kPlanLanes && C->lv[l1].n_steps == C->lv[l0].n_steps &&
+               C->lv[l1].step == C->lv[l0].step)
+            ++l1;
+        LevelHost& h0 = C->lv[l0];
+        int64_t k = std::min(nsteps, h0.n_steps - h0.step);
+        while (k > 0) {
+            const int64_t ns = std::min<int64_t>(k, int64_t(1) << 20);
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            const bool time_this = C->timing > 0 && !std::any_of(C->lv.begin(), C->lv.end(), [](const LevelHost& x) {
+                return x.plan == kPlanStream || x.plan == kPlanSlab;
+            });
+            if (time_this) {
+                e0 = next_event(C);
+                e1 = next_event(C);
+                if (!e0 || !e1) return fail(SLLG_E_HIP, "event pool");
+                HIP_OK(hipEventRecord(e0, C->stream));
+            }
+            HIP_OK(dispatch_lanes(C, l0, l1, h0.step, ns));
+            if (time_this) {
+                HIP_OK(hipEventRecord(e1, C->stream));
+                C->ev_launches.push_back(1);
+                int64_t cells = 0;
+                for (int l = l0; l < l1; ++l) cells += C->lv[l].ninst;
+                C->timed_cells = cells * ns;
+            }
+            for (int l = l0; l < l1; ++l) C->lv[l].step += ns;
+            k -= ns;
+        }
+        l0 = l1;
     }
     // resident sets: launches of at most 32768 steps
     for (const auto& rs : C->res_sets) {
@@ -1571,9 +1622,13 @@ int init_impl(const sllg_material* mat, const sllg_level* levels, int32_t n_leve
     }
     C->use_graph = !(options & SLLG_OPT_NO_GRAPH);
     C->h_levels.resize(n_levels);
+    // a context of single-cell levels only runs one realization per lane;
+    // single cells beside bigger levels share the resident launch instead
+    bool all_single = true;
+    for (const LevelHost& h : C->lv) all_single = all_single && h.ncell == 1;
     for (int i = 0; i < n_levels; ++i) {
         LevelHost& h = C->lv[i];
-        h.plan = resident_fits(h, C->max_lds) ? kPlanResident : kPlanStream;
+        h.plan = all_single ? kPlanLanes : resident_fits(h, C->max_lds) ? kPlanResident : kPlanStream;
         if (h.plan == kPlanStream) default_stream_shape(C, h);
     }
     rc = replan(C);
@@ -1836,6 +1891,8 @@ int sllg_level_kernel(const sllg_ctx* C, int32_t level, char* name, int32_t cap)
         const SlabKernel& k = kSlabKernels[h.slab_kernel];
         snprintf(buf, sizeof(buf), "%s<%d,%d> tz %d steps/launch %d", k.kind == 0 ? "k_slab" : "k_slab2", k.nt, k.k,
                  h.slab_tz, kSlabChunk);
+    } else if (h.plan == kPlanLanes) {
+        snprintf(buf, sizeof(buf), "k_lanes<%d>", kLanesThreads);
     } else {
         for (const auto& rs : C->res_sets)
             if (std::find(rs.levels.begin(), rs.levels.end(), level) != rs.levels.end())
@@ -1892,11 +1949,16 @@ int sllg_set_plan(sllg_ctx* C, int32_t level, int32_t plan)
     LevelHost& h = C->lv[level];
     if (plan == kPlanAuto) {
         h.forced = 0;
-        plan = resident_fits(h, C->max_lds) ? kPlanResident : kPlanStream;
+        bool all_single = true;
+        for (const LevelHost& x : C->lv) all_single = all_single && x.ncell == 1;
+        plan = all_single ? kPlanLanes : resident_fits(h, C->max_lds) ? kPlanResident : kPlanStream;
     } else if (plan == kPlanResident) {
         if (!resident_fits(h, C->max_lds)) return fail(SLLG_E_INVAL, "level %d does not fit in LDS", level);
         h.forced = 1;
     } else if (plan == kPlanStream) {
+        h.forced = 1;
+    } else if (plan == kPlanLanes) {
+        if (h.ncell != 1) return fail(SLLG_E_INVAL, "level %d is not a single cell (plan 4)", level);
         h.forced = 1;
     } else if (plan == kPlanSlab) {
         if (!slab_eligible(h.in)) return fail(SLLG_E_INVAL, "level %d cannot use slabs (nx*ny <= 1024, nz >= 4)", level);

@@ -19,7 +19,7 @@ SLLG_OK = 0
 ERRORS = {-1: "SLLG_E_INVAL", -2: "SLLG_E_WORKSPACE", -3: "SLLG_E_CAPACITY",
           -4: "SLLG_E_STATE", -5: "SLLG_E_HIP", -6: "SLLG_E_NUMERIC"}
 WAVES = {"triangle": 0, "cosine": 1, "constant": 2}
-PLAN_AUTO, PLAN_RESIDENT, PLAN_STREAM, PLAN_SLAB = 0, 1, 2, 3
+PLAN_AUTO, PLAN_RESIDENT, PLAN_STREAM, PLAN_SLAB, PLAN_LANES = 0, 1, 2, 3, 4
 OPT_NO_TUNE, OPT_NO_SLAB, OPT_NO_GRAPH, OPT_VERBOSE = 1, 2, 4, 8
 
 

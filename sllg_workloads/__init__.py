@@ -165,3 +165,23 @@ def seeded_unit_vectors(n: int, seed: int):
     v = rng.normal(size=(n, 3))
     v /= np.linalg.norm(v, axis=1, keepdims=True)
     return v
+
+
+def macrospin_pair(sr_Oe_per_ns: float, alpha: float, T_K: float = 310.0, n_real: int = 256,
+                   dt_s: float = 1e-12, n_points: int = 4000, seed_base: int = 1,
+                   Hmax_Oe: float = 500.0, wave: str = "cosine") -> dict:
+    """The single-macrospin limit of the rod (one cubic cell with the rod's
+    volume, b = 10752^(1/3), easy axis along z, no cone) under the paper's
+    cosine sweep of +-Hmax at sweep rate SR with damping alpha: one point of
+    a sweep-rate / damping scan (Sharrock's law, Eq. 14).  Time steps of
+    1 ps resolve the precession at the largest field (about 0.014 rad per
+    step); the loop keeps about n_points recorded points (the area and the
+    per-realization crossings use every step)."""
+    period_steps = 4.0 * Hmax_Oe / (sr_Oe_per_ns * 1e9) / dt_s
+    rec = max(1, int(period_steps // n_points))
+    return dict(
+        material=dict(BASE_MATERIAL, T_K=T_K, Hmax_Oe=Hmax_Oe, sweep_Oe_per_ns=sr_Oe_per_ns, wave=wave),
+        levels=[_level(1, 1, 1, b=B_SINGLE_CELL, alpha=alpha, dt_s=dt_s, n_real=n_real,
+                       seed_base=seed_base, record_every=rec)],
+        ckpt_every=0,
+    )
