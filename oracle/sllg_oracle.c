@@ -220,16 +220,33 @@ static void neighbour_diff(const orc_level* L, const double* v, int x, int y,
 /* Grids of at least this many cells spread their per-cell loops over the
  * OpenMP threads (each cell is computed independently, so the result does not
  * depend on the thread count).  Inside a parallel region over realizations
- * these loops run on the calling thread only (no nested parallelism). */
+ * these loops run on the calling thread only (no nested parallelism).
+ * Smaller grids never enter a parallel region (even an inactive one costs
+ * about a microsecond, more than a single cell's step). */
 #define ORC_CELL_PAR 65536
+
+/* for (int64_t VAR = 0; VAR < N; ++VAR) { BODY }, over the threads when BIG */
+#ifdef _OPENMP
+#define ORC_LOOP(BIG, N, VAR, ...)                                            \
+    do {                                                                      \
+        if (BIG) {                                                            \
+            _Pragma("omp parallel for schedule(static)")                      \
+            for (int64_t VAR = 0; VAR < (N); ++VAR) { __VA_ARGS__ }           \
+        } else {                                                              \
+            for (int64_t VAR = 0; VAR < (N); ++VAR) { __VA_ARGS__ }           \
+        }                                                                     \
+    } while (0)
+#else
+#define ORC_LOOP(BIG, N, VAR, ...)                                            \
+    do { for (int64_t VAR = 0; VAR < (N); ++VAR) { __VA_ARGS__ } } while (0)
+#endif
 
 void orc_effective_field(const orc_level* L, const double* u, const double* m,
                          double hz, const double* hth, double* H)
 {
-#ifdef _OPENMP
-#pragma omp parallel for schedule(static) if ((int64_t)L->nx * L->ny * L->nz >= ORC_CELL_PAR)
-#endif
-    for (int z = 0; z < L->nz; ++z)
+    const int big = (int64_t)L->nx * L->ny * L->nz >= ORC_CELL_PAR;
+    ORC_LOOP(big, L->nz, zz,
+        const int z = (int)zz;
         for (int y = 0; y < L->ny; ++y)
             for (int x = 0; x < L->nx; ++x) {
                 int64_t i = x + (int64_t)L->nx * (y + (int64_t)L->ny * z);
@@ -243,6 +260,7 @@ void orc_effective_field(const orc_level* L, const double* u, const double* m,
                                    (hth ? hth[3 * i + c] : 0.0);
                 H[3 * i + 2] += hz;
             }
+    );
 }
 
 static void cross(const double a[3], const double b[3], double o[3])
@@ -273,10 +291,7 @@ static void thermal_field(const orc_level* L, uint64_t seed, int64_t n,
                           double* hth, double* xi_out)
 {
     int64_t N = (int64_t)L->nx * L->ny * L->nz;
-#ifdef _OPENMP
-#pragma omp parallel for schedule(static) if (N >= ORC_CELL_PAR)
-#endif
-    for (int64_t i = 0; i < N; ++i) {
+    ORC_LOOP(N >= ORC_CELL_PAR, N, i,
         double xi[3] = {0.0, 0.0, 0.0};
         if (L->sigma != 0.0 || xi_out)
             orc_normals(seed, (uint32_t)L->level_tag, (uint32_t)i, (uint64_t)n, xi);
@@ -284,7 +299,7 @@ static void thermal_field(const orc_level* L, uint64_t seed, int64_t n,
             hth[3 * i + c] = L->sigma * xi[c];
             if (xi_out) xi_out[3 * i + c] = xi[c];
         }
-    }
+    );
 }
 
 /* Scratch for one step of one grid. */
@@ -321,22 +336,17 @@ static void heun_step_ws(const orc_level* L, const double* u, uint64_t seed,
     double hz1 = orc_applied_field(L, n + 1);
     thermal_field(L, seed, n, w->hth, w->xi);
     orc_effective_field(L, u, m, hz0, w->hth, w->H);
-#ifdef _OPENMP
-#pragma omp parallel for schedule(static) if (N >= ORC_CELL_PAR)
-#endif
-    for (int64_t i = 0; i < N; ++i) {
+    const int big = N >= ORC_CELL_PAR;
+    ORC_LOOP(big, N, i,
         llg_rhs(L, m + 3 * i, w->H + 3 * i, w->f + 3 * i);
         double p[3];
         for (int c = 0; c < 3; ++c) p[c] = m[3 * i + c] + L->dt * w->f[3 * i + c];
         double pn = sqrt(dot3(p, p));
         w->pn[i] = pn;
         for (int c = 0; c < 3; ++c) w->mp[3 * i + c] = p[c] / pn;
-    }
+    );
     orc_effective_field(L, u, w->mp, hz1, w->hth, w->Hp);
-#ifdef _OPENMP
-#pragma omp parallel for schedule(static) if (N >= ORC_CELL_PAR)
-#endif
-    for (int64_t i = 0; i < N; ++i) {
+    ORC_LOOP(big, N, i,
         llg_rhs(L, w->mp + 3 * i, w->Hp + 3 * i, w->fp + 3 * i);
         double q[3];
         for (int c = 0; c < 3; ++c)
@@ -344,7 +354,7 @@ static void heun_step_ws(const orc_level* L, const double* u, uint64_t seed,
         double qn = sqrt(dot3(q, q));
         w->qn[i] = qn;
         for (int c = 0; c < 3; ++c) m_out[3 * i + c] = q[c] / qn;
-    }
+    );
 }
 
 int orc_heun_step(const orc_level* L, const double* u, uint64_t seed, int64_t n,
