@@ -51,7 +51,7 @@ class Level(C.Structure):
         ("alpha", C.c_double), ("sigma", C.c_double), ("dt", C.c_double),
         ("hz_amp", C.c_double), ("n_period", C.c_int64), ("wave", C.c_int32),
         ("axis", C.c_double * 3), ("cone_deg", C.c_double),
-        ("axis_seed", C.c_uint64),
+        ("axis_seed", C.c_uint64), ("demag_ms", C.c_double),
     ]
 
 
@@ -81,6 +81,8 @@ def lib():
             "orc_run": (C.c_int, [lp, dp, C.c_uint64, C.c_int64, C.c_int64, dp, dp]),
             "orc_run_batch": (C.c_int, [lp, dp, u64p, C.c_int32, C.c_int64, dp, dp, C.c_int32]),
             "orc_max_threads": (C.c_int, []),
+            "orc_newell": (None, [C.c_int, C.c_int, C.c_int, dp]),
+            "orc_demag_tensor": (None, [lp, dp]),
             "orc_loop_stats": (None, [dp, dp, C.c_int64, dp]),
             "orc_adjoint": (C.c_int, [lp, dp, C.c_uint64, C.c_int64, dp, C.c_int32, dp, dp]),
             "orc_adjoint_batch": (C.c_int, [lp, dp, u64p, C.c_int32, C.c_int64, dp, C.c_int32, dp, dp, C.c_int32]),
@@ -120,6 +122,7 @@ def level_struct(lv: dict) -> Level:
     s.axis[0], s.axis[1], s.axis[2] = ax
     s.cone_deg = lv.get("cone_deg", 0.0)
     s.axis_seed = int(lv.get("axis_seed", 0))
+    s.demag_ms = float(lv.get("demag_ms", 0.0))
     return s
 
 
@@ -170,6 +173,23 @@ def make_axes(lv):
     s = level_struct(lv)
     lib().orc_make_axes(C.byref(s), _dp(u))
     return u
+
+
+def newell(X, Y, Z):
+    """Demagnetising tensor (xx, yy, zz, xy, xz, yz) between two unit cubes
+    whose centres are (X, Y, Z) cell edges apart (Newell et al. 1993)."""
+    o = (C.c_double * 6)()
+    lib().orc_newell(int(X), int(Y), int(Z), o)
+    return np.array(list(o))
+
+
+def demag_tensor(lv):
+    """(2nz-1, 2ny-1, 2nx-1, 6) table of the tensor over every cell offset."""
+    s = level_struct(lv)
+    shape = (2 * int(lv["nz"]) - 1, 2 * int(lv["ny"]) - 1, 2 * int(lv["nx"]) - 1, 6)
+    T = np.zeros(shape)
+    lib().orc_demag_tensor(C.byref(s), _dp(T))
+    return T
 
 
 def applied_field(lv, n):

@@ -162,6 +162,8 @@ def compile_level(material: dict, level: dict, level_index: int = 0) -> dict:
         axis=tuple(m["easy_axis"]), cone_deg=level.get("cone_deg", 0.0),
         axis_seed=level.get("axis_seed", 0),
         Hmax_Oe=m["Hmax_Oe"], T=m["T_K"], Ms0=m["Ms0"],
+        # magnetostatics (beyond the paper): the field -Ms N m of the cells
+        demag_ms=Ms if m.get("demag", False) else 0.0,
     )
 
 

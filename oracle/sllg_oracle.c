@@ -53,6 +53,7 @@ typedef struct {
     double axis[3];        /* easy axis (unit) */
     double cone_deg;       /* > 0: per-cell axes in a uniform cone about axis */
     uint64_t axis_seed;
+    double demag_ms;       /* A/m: Ms of the magnetostatic field; 0 = none */
 } orc_level;
 
 enum { ORC_TAG_NOISE = 1, ORC_TAG_AXIS = 2 };
@@ -241,8 +242,126 @@ static void neighbour_diff(const orc_level* L, const double* v, int x, int y,
     do { for (int64_t VAR = 0; VAR < (N); ++VAR) { __VA_ARGS__ } } while (0)
 #endif
 
+/* ------------------------------------------------------------------------ */
+/* Magnetostatic (demagnetising) field of uniformly magnetised cubic cells     */
+/* ------------------------------------------------------------------------ */
+/* Beyond the paper (it leaves magnetostatics out and folds shape anisotropy
+ * into K, material paragraph and closing discussion).  The field of cell j on
+ * cell i, averaged over cell i, is -Ms N(r_i - r_j) m_j with N the demagnetising
+ * tensor of two cubes (Newell, Williams and Dunlop, J. Geophys. Res. 98, 9551
+ * (1993)): N_xx = -(1/(4 pi V)) D2x D2y D2z f and N_xy = -(1/(4 pi V)) D2 D2
+ * D2 g, where D2 is the second difference (h(s + a) - 2 h(s) + h(s - a)) in
+ * each coordinate and f, g are Newell's closed-form double integrals below.
+ * Lengths are in units of the cell edge (V = 1).  Long double: the 27 terms
+ * of the stencil cancel to ~r^-3 from values ~r^2. */
+typedef long double ld;
+
+static ld newell_f(ld x, ld y, ld z)
+{
+    x = fabsl(x); y = fabsl(y); z = fabsl(z);
+    ld x2 = x * x, y2 = y * y, z2 = z * z;
+    ld R = sqrtl(x2 + y2 + z2);
+    ld r = (2 * x2 - y2 - z2) * R / 6;
+    if (y > 0 && x2 + z2 > 0) r += y / 2 * (z2 - x2) * asinhl(y / sqrtl(x2 + z2));
+    if (z > 0 && x2 + y2 > 0) r += z / 2 * (y2 - x2) * asinhl(z / sqrtl(x2 + y2));
+    if (x > 0 && y > 0 && z > 0) r -= x * y * z * atanl(y * z / (x * R));
+    return r;
+}
+
+static ld newell_g(ld x, ld y, ld z)
+{
+    ld sg = ((x < 0) != (y < 0)) ? -1 : 1;
+    x = fabsl(x); y = fabsl(y); z = fabsl(z);
+    ld x2 = x * x, y2 = y * y, z2 = z * z;
+    ld R = sqrtl(x2 + y2 + z2);
+    ld r = -x * y * R / 3;
+    if (x > 0 && y > 0 && z > 0) r += x * y * z * asinhl(z / sqrtl(x2 + y2));
+    if (y > 0 && y2 + z2 > 0 && x > 0) r += y / 6 * (3 * z2 - y2) * asinhl(x / sqrtl(y2 + z2));
+    if (x > 0 && x2 + z2 > 0 && y > 0) r += x / 6 * (3 * z2 - x2) * asinhl(y / sqrtl(x2 + z2));
+    if (z > 0 && x > 0 && y > 0) r -= z * z2 / 6 * atanl(x * y / (z * R));
+    if (z > 0 && y > 0 && x > 0) r -= z * y2 / 2 * atanl(x * z / (y * R));
+    if (z > 0 && x > 0 && y > 0) r -= z * x2 / 2 * atanl(y * z / (x * R));
+    return sg * r;
+}
+
+/* -(1/4pi) sum over the 27-point stencil with weights (1, -2, 1)^3 */
+static ld newell_stencil(ld (*fn)(ld, ld, ld), ld X, ld Y, ld Z)
+{
+    static const ld w[3] = {1, -2, 1};
+    ld acc = 0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            for (int k = 0; k < 3; ++k)
+                acc += w[i] * w[j] * w[k] * fn(X + i - 1, Y + j - 1, Z + k - 1);
+    return -acc / (4 * (ld)M_PI);
+}
+
+/* The tensor for integer offsets (X, Y, Z) in cell edges: out = xx, yy, zz,
+ * xy, xz, yz (symmetric). */
+void orc_newell(int X, int Y, int Z, double out[6])
+{
+    out[0] = (double)newell_stencil(newell_f, X, Y, Z);
+    out[1] = (double)newell_stencil(newell_f, Y, X, Z);
+    out[2] = (double)newell_stencil(newell_f, Z, Y, X);
+    out[3] = (double)newell_stencil(newell_g, X, Y, Z);
+    out[4] = (double)newell_stencil(newell_g, X, Z, Y);
+    out[5] = (double)newell_stencil(newell_g, Y, Z, X);
+}
+
+/* Table of N for every offset between two cells of the grid:
+ * T[6 * (((dz + nz - 1) * (2 ny - 1) + dy + ny - 1) * (2 nx - 1) + dx + nx - 1) + c]. */
+void orc_demag_tensor(const orc_level* L, double* T)
+{
+    int64_t wx = 2 * L->nx - 1, wy = 2 * L->ny - 1, wz = 2 * L->nz - 1;
+    for (int64_t k = 0; k < wz; ++k)
+        for (int64_t j = 0; j < wy; ++j)
+            for (int64_t i = 0; i < wx; ++i)
+                orc_newell((int)(i - L->nx + 1), (int)(j - L->ny + 1), (int)(k - L->nz + 1),
+                           T + 6 * ((k * wy + j) * wx + i));
+}
+
+static double* demag_table(const orc_level* L)
+{
+    if (L->demag_ms == 0.0) return NULL;
+    int64_t n = (2 * (int64_t)L->nx - 1) * (2 * L->ny - 1) * (2 * L->nz - 1);
+    double* T = (double*)malloc(sizeof(double) * 6 * (size_t)n);
+    if (T) orc_demag_tensor(L, T);
+    return T;
+}
+
+/* Hd_i = -Ms sum_j N(r_i - r_j) m_j, a plain double sum over all cells */
+static void demag_field(const orc_level* L, const double* T, const double* m, double* Hd)
+{
+    int64_t nx = L->nx, ny = L->ny, nz = L->nz, N = nx * ny * nz;
+    int64_t wx = 2 * nx - 1, wy = 2 * ny - 1;
+    ORC_LOOP(N >= ORC_CELL_PAR, N, i,
+        int64_t xi = i % nx, yi = (i / nx) % ny, zi = i / (nx * ny);
+        double h[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < N; ++j) {
+            int64_t xj = j % nx, yj = (j / nx) % ny, zj = j / (nx * ny);
+            const double* t = T + 6 * (((zi - zj + nz - 1) * wy + yi - yj + ny - 1) * wx + xi - xj + nx - 1);
+            const double* v = m + 3 * j;
+            h[0] += t[0] * v[0] + t[3] * v[1] + t[4] * v[2];
+            h[1] += t[3] * v[0] + t[1] * v[1] + t[5] * v[2];
+            h[2] += t[4] * v[0] + t[5] * v[1] + t[2] * v[2];
+        }
+        for (int c = 0; c < 3; ++c) Hd[3 * i + c] = -L->demag_ms * h[c];
+    );
+}
+
+static void effective_field_t(const orc_level* L, const double* u, const double* m,
+                              double hz, const double* hth, double* H, const double* T);
+
 void orc_effective_field(const orc_level* L, const double* u, const double* m,
                          double hz, const double* hth, double* H)
+{
+    double* T = demag_table(L);
+    effective_field_t(L, u, m, hz, hth, H, T);
+    free(T);
+}
+
+static void effective_field_t(const orc_level* L, const double* u, const double* m,
+                              double hz, const double* hth, double* H, const double* T)
 {
     const int big = (int64_t)L->nx * L->ny * L->nz >= ORC_CELL_PAR;
     ORC_LOOP(big, L->nz, zz,
@@ -261,6 +380,14 @@ void orc_effective_field(const orc_level* L, const double* u, const double* m,
                 H[3 * i + 2] += hz;
             }
     );
+    if (T) {
+        int64_t N = (int64_t)L->nx * L->ny * L->nz;
+        double* Hd = (double*)malloc(sizeof(double) * 3 * (size_t)N);
+        if (!Hd) return;
+        demag_field(L, T, m, Hd);
+        for (int64_t k = 0; k < 3 * N; ++k) H[k] += Hd[k];
+        free(Hd);
+    }
 }
 
 static void cross(const double a[3], const double b[3], double o[3])
@@ -305,12 +432,16 @@ static void thermal_field(const orc_level* L, uint64_t seed, int64_t n,
 /* Scratch for one step of one grid. */
 typedef struct {
     double *hth, *xi, *H, *f, *mp, *Hp, *fp, *pn, *qn;
+    double* demag;   /* tensor table when the level has magnetostatics */
 } step_ws;
 
-static int ws_alloc(step_ws* w, int64_t N)
+static int ws_alloc(step_ws* w, const orc_level* L)
 {
+    int64_t N = (int64_t)L->nx * L->ny * L->nz;
     double* blk = (double*)malloc(sizeof(double) * (size_t)(3 * N * 7 + 2 * N));
     if (!blk) return -1;
+    w->demag = demag_table(L);
+    if (L->demag_ms != 0.0 && !w->demag) { free(blk); return -1; }
     w->hth = blk;
     w->xi = blk + 3 * N;
     w->H = blk + 6 * N;
@@ -323,7 +454,7 @@ static int ws_alloc(step_ws* w, int64_t N)
     return 0;
 }
 
-static void ws_free(step_ws* w) { free(w->hth); }
+static void ws_free(step_ws* w) { free(w->hth); free(w->demag); }
 
 /* One Heun step n -> n+1.  Predictor with the field at t_n, corrector with
  * the field at t_{n+1}; the same thermal field in both stages; |m| = 1 is
@@ -335,7 +466,7 @@ static void heun_step_ws(const orc_level* L, const double* u, uint64_t seed,
     double hz0 = orc_applied_field(L, n);
     double hz1 = orc_applied_field(L, n + 1);
     thermal_field(L, seed, n, w->hth, w->xi);
-    orc_effective_field(L, u, m, hz0, w->hth, w->H);
+    effective_field_t(L, u, m, hz0, w->hth, w->H, w->demag);
     const int big = N >= ORC_CELL_PAR;
     ORC_LOOP(big, N, i,
         llg_rhs(L, m + 3 * i, w->H + 3 * i, w->f + 3 * i);
@@ -345,7 +476,7 @@ static void heun_step_ws(const orc_level* L, const double* u, uint64_t seed,
         w->pn[i] = pn;
         for (int c = 0; c < 3; ++c) w->mp[3 * i + c] = p[c] / pn;
     );
-    orc_effective_field(L, u, w->mp, hz1, w->hth, w->Hp);
+    effective_field_t(L, u, w->mp, hz1, w->hth, w->Hp, w->demag);
     ORC_LOOP(big, N, i,
         llg_rhs(L, w->mp + 3 * i, w->Hp + 3 * i, w->fp + 3 * i);
         double q[3];
@@ -361,7 +492,7 @@ int orc_heun_step(const orc_level* L, const double* u, uint64_t seed, int64_t n,
                   const double* m, double* m_out)
 {
     step_ws w;
-    if (ws_alloc(&w, (int64_t)L->nx * L->ny * L->nz)) return -1;
+    if (ws_alloc(&w, L)) return -1;
     heun_step_ws(L, u, seed, n, m, m_out, &w);
     ws_free(&w);
     return 0;
@@ -375,7 +506,8 @@ static double mean_mz(const double* m, int64_t N)
 }
 
 /* Reduced energy e = E/(mu0 Ms V) for a constant applied field hz along z:
- * e = -sum m.H_app - (hk/2) sum (m.u)^2 + (c_ex/2) sum_<ij> |m_i - m_j|^2. */
+ * e = -sum m.H_app - (hk/2) sum (m.u)^2 + (c_ex/2) sum_<ij> |m_i - m_j|^2
+ *     (+ (Ms/2) sum_ij m_i . N(r_i - r_j) m_j with magnetostatics). */
 double orc_energy(const orc_level* L, const double* u, const double* m, double hz)
 {
     int64_t nx = L->nx, ny = L->ny, nz = L->nz;
@@ -402,6 +534,17 @@ double orc_energy(const orc_level* L, const double* u, const double* m, double h
                     e += 0.5 * L->c_ex * dd;
                 }
             }
+    if (L->demag_ms != 0.0) {
+        /* magnetostatic self-energy e = -(1/2) sum_i m_i . Hd_i */
+        int64_t N = nx * ny * nz;
+        double* T = demag_table(L);
+        double* Hd = (double*)malloc(sizeof(double) * 3 * (size_t)N);
+        if (!T || !Hd) { free(T); free(Hd); return NAN; }
+        demag_field(L, T, m, Hd);
+        for (int64_t i = 0; i < N; ++i) e -= 0.5 * dot3(m + 3 * i, Hd + 3 * i);
+        free(T);
+        free(Hd);
+    }
     return e;
 }
 
@@ -413,7 +556,7 @@ int orc_run(const orc_level* L, const double* u, uint64_t seed, int64_t n0,
 {
     int64_t N = (int64_t)L->nx * L->ny * L->nz;
     step_ws w;
-    if (ws_alloc(&w, N)) return -1;
+    if (ws_alloc(&w, L)) return -1;
     double* tmp = (double*)malloc(sizeof(double) * (size_t)(3 * N));
     if (!tmp) { ws_free(&w); return -1; }
     if (mbar) mbar[0] = mean_mz(m, N);
@@ -566,6 +709,7 @@ int orc_adjoint(const orc_level* L, const double* u, uint64_t seed,
                 double* mbar)
 {
     int64_t N = (int64_t)L->nx * L->ny * L->nz;
+    if (L->demag_ms != 0.0) return -2;   /* the adjoint has no magnetostatic term */
     size_t st = (size_t)(3 * N);
     double* traj = (double*)malloc(sizeof(double) * st * (size_t)(nsteps + 1));
     double* lam = (double*)malloc(sizeof(double) * st * (size_t)nloss);
@@ -574,7 +718,7 @@ int orc_adjoint(const orc_level* L, const double* u, uint64_t seed,
     double* tmp = (double*)malloc(sizeof(double) * st);
     double* ex = (double*)malloc(sizeof(double) * st);
     step_ws ws;
-    if (!traj || !lam || !mb || !Hb || !tmp || !ex || ws_alloc(&ws, N)) {
+    if (!traj || !lam || !mb || !Hb || !tmp || !ex || ws_alloc(&ws, L)) {
         free(traj); free(lam); free(mb); free(Hb); free(tmp); free(ex);
         return -1;
     }
