@@ -9,7 +9,13 @@ coercive field reproduce a target, e.g. the loops of the fine (b = 1) grid.
 ``fit_level`` runs Levenberg-Marquardt steps on the residuals
 (S - S*, w (Hc - Hc*)) in the logarithms of the fitted parameters; a trial
 point costs one forward sweep of the level, an accepted one also an adjoint
-sweep, both on the GPU through the C ABI.
+sweep, both on the GPU through the C ABI.  Targets are in simulation units,
+or in physical units (H / zeta, Eq. 10, and m times the Eq. 13 factor
+c_M = 1 - delta (1 - zeta)).  In physical units the loop-height weight delta
+of Eq. 13 can be fitted too: at every trial point it is set so that the
+coarse loop's remanence c_M M_r matches the target remanence (c_M scales the
+whole loop, so its height, not its width; the adjoint gives the area and
+coercive-field gradients, and c_M enters the area residual as a factor).
 """
 from __future__ import annotations
 
@@ -20,20 +26,32 @@ from .sllg import loop_area_hc
 PARAMS = ("K", "A", "alpha", "ms_scale")
 
 
-def _evaluate(material, level, vals, fit, target, hc_weight, ckpt_every):
+def _evaluate(material, level, vals, fit, target, hc_weight, ckpt_every, phys=None):
     """Residuals (S - S*, w (Hc - Hc*)) at vals, and a function that returns
     their Jacobian in the logarithms of the fitted parameters (one adjoint
-    sweep; None where a residual is not finite)."""
+    sweep; None where a residual is not finite).  phys: None (simulation
+    units) or dict(mr_target=None | M_r*) for physical units, with delta
+    fitted to the remanence when mr_target is given."""
     import torch
     x = {k: torch.tensor(vals[k], dtype=torch.float64, requires_grad=k in fit) for k in PARAMS}
-    S, Hc = loop_area_hc(x["K"], x["A"], x["alpha"], x["ms_scale"], material, level, ckpt_every)
+    info = {}
+    S, Hc = loop_area_hc(x["K"], x["A"], x["alpha"], x["ms_scale"], material, level, ckpt_every, info)
     Sv, Hv = float(S.detach()), float(Hc.detach())
-    res, outs, wts = [Sv - target[0]], [S], [1.0]
+    # physical units: S_phys = S_sim c_M / hscale, Hc_phys = Hc_sim / hscale
+    sS, sH, cM, delta = 1.0, 1.0, None, None
+    if phys is not None:
+        hs, z = info["hscale"], info["zeta"]
+        cM = info["cM"]
+        if phys.get("mr_target") is not None and info["Mr_sim"] > 0 and z < 1.0:
+            cM = phys["mr_target"] / info["Mr_sim"]
+            delta = (1.0 - cM) / (1.0 - z)
+        sS, sH = cM / hs, 1.0 / hs
+    res, outs, wts = [sS * Sv - target[0]], [S], [sS]
     if hc_weight > 0 and math.isfinite(target[1]):
         # a loop that stops crossing zero counts as missing the target by Hmax
-        res.append(hc_weight * ((Hv if math.isfinite(Hv) else 1e300) - target[1]))
+        res.append(hc_weight * ((sH * Hv if math.isfinite(Hv) else 1e300) - target[1]))
         outs.append(Hc)
-        wts.append(hc_weight)
+        wts.append(hc_weight * sH)
     res = [min(max(r, -1e30), 1e30) for r in res]
 
     def jacobian():
@@ -45,26 +63,34 @@ def _evaluate(material, level, vals, fit, target, hc_weight, ckpt_every):
             rows.append([wts[j] * float(gi) * vals[k] for gi, k in zip(g, fit)])
         return torch.tensor(rows, dtype=torch.float64)
 
-    return res, jacobian, Sv, Hv
+    out = dict(S=sS * Sv, Hc=sH * Hv if math.isfinite(Hv) else Hv, Mr=info["Mr_sim"] * (cM if cM else 1.0),
+               S_se=sS * info["S_se"], Hc_se=sH * info["Hc_se"], cM=cM, delta=delta)
+    return res, jacobian, out
 
 
 def fit_level(material: dict, level: dict, start: dict, target, fit=("K",), hc_weight=0.0,
-              steps: int = 8, ckpt_every: int = 256, tol: float = 1e-4, max_log_step: float = 0.25):
+              steps: int = 8, ckpt_every: int = 256, tol: float = 1e-4, max_log_step: float = 0.25,
+              units: str = "sim", mr_target=None):
     """Fit the parameters named in ``fit`` (a subset of K, A, alpha,
     ms_scale) of one level so that its ensemble-mean loop has area
-    target[0] and, when hc_weight > 0, coercive field target[1] (simulation
-    units, Oe).  ``start`` holds all four values (K and A simulated, J/m^3
-    and J/m).  Levenberg-Marquardt in the logarithms of the parameters: a
-    step that does not lower the squared residual is undone and the damping
-    raised.  Returns (values, history); history lists the accepted points
-    (values, S, Hc, squared residual).
+    target[0] and, when hc_weight > 0, coercive field target[1] (Oe, in
+    simulation units, or physical units with units="phys").  With
+    units="phys" and ``mr_target`` given, the Eq. 13 weight delta is fitted
+    as well (the coarse loop's remanence matched to mr_target at every
+    point).  ``start`` holds all four values (K and A simulated, J/m^3 and
+    J/m).  Levenberg-Marquardt in the logarithms of the parameters: a step
+    that does not lower the squared residual is undone and the damping
+    raised.  Returns (values, history); values holds delta when it was
+    fitted, history the accepted points (values, S, Hc, Mr, delta, squared
+    residual).
     """
     import torch
+    phys = dict(mr_target=mr_target) if units == "phys" else None
     vals = {k: float(start[k]) for k in PARAMS}
-    res, jac, Sv, Hv = _evaluate(material, level, vals, fit, target, hc_weight, ckpt_every)
+    res, jac, o = _evaluate(material, level, vals, fit, target, hc_weight, ckpt_every, phys)
     J = jac()
     err = sum(r * r for r in res)
-    hist = [dict(vals, S=Sv, Hc=Hv, err=err)]
+    hist = [dict(vals, **o, err=err)]
     mu = 1e-3
     for _ in range(steps):
         if err <= (tol * abs(target[0])) ** 2 or J is None:
@@ -76,23 +102,28 @@ def fit_level(material: dict, level: dict, start: dict, target, fit=("K",), hc_w
         trial = dict(vals)
         for k, d in zip(fit, (dlog * scale).tolist()):
             trial[k] = vals[k] * math.exp(d)
-        res_t, jac_t, S_t, H_t = _evaluate(material, level, trial, fit, target, hc_weight, ckpt_every)
+        res_t, jac_t, o_t = _evaluate(material, level, trial, fit, target, hc_weight, ckpt_every, phys)
         err_t = sum(x * x for x in res_t)
         if err_t < err:
-            vals, res, J, err = trial, res_t, jac_t(), err_t
-            hist.append(dict(vals, S=S_t, Hc=H_t, err=err))
+            vals, res, J, err, o = trial, res_t, jac_t(), err_t, o_t
+            hist.append(dict(vals, **o, err=err))
             mu = max(mu / 3.0, 1e-6)
         else:
             mu *= 10.0
-    return vals, hist
+    out = dict(vals)
+    if o.get("delta") is not None:
+        out["delta"] = o["delta"]
+    return out, hist
 
 
 def fit_coarse_to_fine(material: dict, fine: dict, coarse: dict, fit=("K", "A"), steps: int = 8,
-                       log=print):
+                       fit_delta: bool = False, log=print):
     """Run the fine level once, then fit the coarse level's parameters so
     that its loop reproduces the fine loop's area and coercive field in
     physical units (H / zeta and the Eq. 13 magnetisation factor of each
-    level).  Returns (fine stats, rule values, fitted values, history)."""
+    level); with fit_delta the Eq. 13 weight is fitted to the fine loop's
+    remanence as well.  Returns (fine stats, rule values, fitted values,
+    history)."""
     from .sllg import Sim
     sim = Sim(material, [fine])
     n = int(sim.level_params(0)["n_steps"])
@@ -108,14 +139,12 @@ def fit_coarse_to_fine(material: dict, fine: dict, coarse: dict, fit=("K", "A"),
     sim = Sim(material, [coarse])
     pc = sim.level_params(0)
     sim.close()
-    hs, cM = pc["hscale"], pc["cM"]
-    target = (sf["S_phys"] * hs / cM, sf["Hc_phys"] * hs)
+    target = (sf["S_phys"], sf["Hc_phys"])
     start = dict(K=pc["K"], A=pc["A"], alpha=pc["alpha"], ms_scale=material.get("ms_scale", 1.0))
     vals, hist = fit_level(material, coarse, start, target, fit=fit, hc_weight=target[0] / target[1],
-                           steps=steps)
+                           steps=steps, units="phys", mr_target=sf["Mr_phys"] if fit_delta else None)
     for h in hist:
-        h["S_phys"] = h["S"] * cM / hs
-        h["Hc_phys"] = h["Hc"] / hs
+        h["S_phys"], h["Hc_phys"], h["Mr_phys"] = h["S"], h["Hc"], h["Mr"]
     return sf, start, vals, hist
 
 
@@ -137,8 +166,9 @@ if __name__ == "__main__":
     rule.run_sweep()
     sr = rule.loop(0, -1)[2]
     rule.close()
-    sf, start, vals, hist = fit_coarse_to_fine(mat, fine, coarse,
+    sf, start, vals, hist = fit_coarse_to_fine(mat, fine, coarse, fit_delta="--delta" in sys.argv,
                                                log=lambda s: print(s, file=sys.stderr, flush=True))
     print(json.dumps({"fine_b1": {k: sf[k] for k in keys}, "coarse_b4_rule": {k: sr[k] for k in keys},
                       "rule": start, "fitted": vals,
-                      "history": [{k: h[k] for k in ("K", "A", "S_phys", "Hc_phys", "err")} for h in hist]}))
+                      "history": [{k: h[k] for k in ("K", "A", "S_phys", "Hc_phys", "Mr_phys", "delta", "err")}
+                                  for h in hist]}))

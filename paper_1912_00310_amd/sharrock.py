@@ -62,14 +62,17 @@ def scan(pairs, T_K=310.0, n_real=256, dt_s=1e-12, streams=4, device="cuda:0", l
     # different streams run concurrently (each occupies a few CUs)
     for sr, al, sim in sims:
         sim.run_sweep()
-    out = []
-    for sr, al, sim in sims:
+    out = [None] * len(sims)
+    # the shortest sweeps are read first (progress while the long ones run)
+    order = sorted(range(len(sims)), key=lambda i: sims[i][0], reverse=True)
+    for i in order:
+        sr, al, sim = sims[i]
         _, _, st = sim.loop(0, -1)
         p = sim.level_params(0)
         kv = p["K"] * p["a"] ** 3 / (KB * T_K)
-        out.append(dict(SR=sr, alpha=al, T=T_K, Hc=st["Hc_sim"], Hc_se=st["Hc_se"], S=st["S_sim"],
-                        S_se=st["S_se"], Mr=st["Mr_sim"], H_K=p["hk"] * OE_PER_APM, KV_kT=kv,
-                        n_steps=int(p["n_steps"]), kernel=sim.kernel_name(0)))
+        out[i] = dict(SR=sr, alpha=al, T=T_K, Hc=st["Hc_sim"], Hc_se=st["Hc_se"], S=st["S_sim"],
+                      S_se=st["S_se"], Mr=st["Mr_sim"], H_K=p["hk"] * OE_PER_APM, KV_kT=kv,
+                      n_steps=int(p["n_steps"]), kernel=sim.kernel_name(0))
         if log:
             log(f"SR {sr:g} Oe/ns alpha {al:g}: Hc {st['Hc_sim']:.2f} +- {st['Hc_se']:.2f} Oe, "
                 f"S {st['S_sim']:.1f} +- {st['S_se']:.1f} Oe ({int(p['n_steps'])} steps)")
@@ -88,14 +91,17 @@ def _linfit(x, y):
     return my - b * mx, b
 
 
-def sharrock_check(at_ratio, at_alpha=None, small_alpha=0.1):
+def sharrock_check(at_ratio, at_alpha=None, small_alpha=0.1, h_max=0.95):
     """Fit Eq. 14 to the scans.
 
     at_ratio: results at fixed SR/alpha.  The intercept A of
     (1 - Hc/H_K)^2 = A - (k_B T/KV) ln(1 + alpha^2) is taken from the points
     with alpha <= small_alpha; the law then predicts Hc at every alpha.
     at_alpha: results at one alpha over several SR; the slope of
-    (1 - Hc/H_K)^2 against ln SR is compared with -k_B T/KV.
+    (1 - Hc/H_K)^2 against ln SR, over the points of thermally activated
+    switching (Hc/H_K < h_max: nearer H_K the moment follows the sweep
+    dynamically and the barrier picture no longer applies), is compared with
+    -k_B T/KV.
     """
     rep = {}
     r0 = at_ratio[0]
@@ -110,7 +116,7 @@ def sharrock_check(at_ratio, at_alpha=None, small_alpha=0.1):
             pred.append(dict(alpha=r["alpha"], SR=r["SR"], Hc=r["Hc"], Hc_se=r["Hc_se"], Hc_eq14=hc))
         rep["fixed_ratio"] = dict(A=A, kT_KV=kt_kv, points=pred)
     if at_alpha:
-        pts = [r for r in at_alpha if math.isfinite(r["Hc"])]
+        pts = [r for r in at_alpha if math.isfinite(r["Hc"]) and r["Hc"] / r["H_K"] < h_max]
         x = [math.log(r["SR"]) for r in pts]
         y = [(1 - r["Hc"] / r["H_K"]) ** 2 for r in pts]
         if len(pts) >= 2:
@@ -127,7 +133,7 @@ def main():
     ap.add_argument("--ratio", type=float, default=2.5, help="SR/alpha, Oe/ns")
     ap.add_argument("--alphas", default="0.01,0.03,0.1,0.3,1,3,10")
     ap.add_argument("--fixed-alpha", type=float, default=0.1)
-    ap.add_argument("--srs", default="0.25,2.5,25,250", help="sweep rates at the fixed alpha, Oe/ns")
+    ap.add_argument("--srs", default="0.025,0.075,0.25,0.75,2.5", help="sweep rates at the fixed alpha, Oe/ns")
     ap.add_argument("--n-real", type=int, default=256)
     ap.add_argument("--dt", type=float, default=1e-12)
     a = ap.parse_args()

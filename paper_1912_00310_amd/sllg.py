@@ -357,7 +357,7 @@ def _loop_function():
         """
 
         @staticmethod
-        def forward(ctx, K, A, alpha, ms_scale, material, level, ckpt_every=256):
+        def forward(ctx, K, A, alpha, ms_scale, material, level, ckpt_every=256, info=None):
             mat = dict(material, K0=float(K), A0=float(A), ms_scale=float(ms_scale), scale_AK=False,
                        sr_ref_Oe_per_ns=0.0)
             # the adjoint weights every step of the loop: record every step
@@ -365,6 +365,11 @@ def _loop_function():
             sim = Sim(mat, [lvd], ckpt_every=ckpt_every)
             sim.run_sweep()
             st = sim.loop(0, -1)[2]
+            if info is not None:
+                # the whole statistics record and the level's loop scales
+                info.update(st)
+                p = sim.level_params(0)
+                info.update(hscale=p["hscale"], cM=p["cM"], zeta=p["zeta"])
             ctx.sim = sim
             return (torch.tensor(st["S_sim"], dtype=torch.float64),
                     torch.tensor(st["Hc_sim"], dtype=torch.float64))
@@ -381,7 +386,7 @@ def _loop_function():
             g = gS.double() * torch.tensor(ga, dtype=torch.float64)
             if float(gHc) != 0.0:
                 g = g + gHc.double() * torch.tensor(gh, dtype=torch.float64)
-            return g[0], g[1], g[2], g[3], None, None, None
+            return g[0], g[1], g[2], g[3], None, None, None, None
 
     return SllgLoop
 
@@ -389,10 +394,13 @@ def _loop_function():
 _SLLG_LOOP = None
 
 
-def loop_area_hc(K, A, alpha, ms_scale, material: dict, level: dict, ckpt_every: int = 256):
+def loop_area_hc(K, A, alpha, ms_scale, material: dict, level: dict, ckpt_every: int = 256,
+                 info: dict | None = None):
     """(S_sim, Hc_sim) = SllgLoop.apply(K, A, alpha, ms_scale, ...): the
-    differentiable loop of one level (see SllgLoop)."""
+    differentiable loop of one level (see SllgLoop).  ``info``, if given, is
+    filled with the loop's statistics (sllg_loop) and the level's scales
+    hscale (zeta of Eq. 10), cM (Eq. 13 factor) and zeta."""
     global _SLLG_LOOP
     if _SLLG_LOOP is None:
         _SLLG_LOOP = _loop_function()
-    return _SLLG_LOOP.apply(K, A, alpha, ms_scale, material, level, ckpt_every)
+    return _SLLG_LOOP.apply(K, A, alpha, ms_scale, material, level, ckpt_every, info)

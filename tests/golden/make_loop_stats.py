@@ -36,6 +36,15 @@ SUBSETS = {
     "multilevel_ens256": [8, 16, 32, 32],
 }
 
+# single-cell sweep-rate / damping scans (sllg_workloads.macrospin_pair):
+# (T, [(SR Oe/ns, alpha), ...]), 32 realizations each
+MACROSPIN = {
+    "sharrock_T100": (100.0, [(0.075, 0.03), (0.25, 0.1), (0.75, 0.3), (2.5, 1.0), (7.5, 3.0), (25.0, 10.0),
+                              (0.75, 0.1), (2.5, 0.1)]),
+    "sharrock_T310": (310.0, [(0.075, 0.03), (0.25, 0.1), (0.75, 0.3), (2.5, 1.0), (7.5, 3.0), (25.0, 10.0)]),
+}
+MACROSPIN_REAL = 32
+
 
 def oracle_digest():
     h = hashlib.sha256()
@@ -77,9 +86,63 @@ def level_stats(wl, i, k, threads):
     }
 
 
+def streamed_stats(wl, k, threads):
+    """As level_stats for one level, holding one realization's loop at a time
+    (long single-cell sweeps): the realizations run in a thread pool (the C
+    oracle releases the GIL) and the mean loop is accumulated."""
+    from concurrent.futures import ThreadPoolExecutor
+    lvd = wl["levels"][0]
+    lv = gk.compile_level(wl["material"], lvd, 0)
+    seeds = [lvd["seed_base"] + r for r in range(k)]
+    t = time.time()
+    H = oracle.field_schedule_Oe(lv)
+    N = lv["nx"] * lv["ny"] * lv["nz"]
+    total = np.zeros(lv["n_steps"] + 1)
+    per = []
+
+    def one(seed):
+        _, mb = oracle.run(lv, seed, 0, lv["n_steps"], np.tile([0.0, 0.0, 1.0], (N, 1)))
+        return seed, oracle.loop_stats(H, mb), mb
+
+    with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+        for seed, st, mb in ex.map(one, seeds):
+            per.append(st)
+            total += mb
+    mean = oracle.loop_stats(H, total / k)
+    el = time.time() - t
+
+    def se(a):
+        a = [x for x in a if math.isfinite(x)]
+        return float(np.std(a, ddof=1) / math.sqrt(len(a))) if len(a) > 1 else None
+
+    S_r = [p["S"] for p in per]
+    Hc_r = [p["Hc"] for p in per]
+    return {
+        "grid": [lv["nx"], lv["ny"], lv["nz"]], "b": lv["b"], "n_steps": lv["n_steps"], "seeds": seeds,
+        "alpha": lv["alpha"], "dt": lv["dt"], "S": S_r, "Hc": [nan_to_none(x) for x in Hc_r],
+        "n_cross_desc": [int(p["n_cross_desc"]) for p in per], "n_cross_asc": [int(p["n_cross_asc"]) for p in per],
+        "mean_loop": {"S_sim": mean["S"], "Hc": nan_to_none(mean["Hc"]), "Mr": nan_to_none(mean["Mr"])},
+        "S_se": se(S_r), "Hc_se": se(Hc_r), "oracle_seconds": round(el, 1),
+    }
+
+
 def main(names):
     threads = oracle.max_threads()
     for name in names:
+        if name in MACROSPIN:
+            T, pairs = MACROSPIN[name]
+            out = {"_source": "FP64 oracle (oracle/), written by tests/golden/make_loop_stats.py",
+                   "workload": name, "oracle_sha256": oracle_digest(), "threads": threads, "pairs": []}
+            for sr, al in pairs:
+                print(f"{name}: SR {sr} alpha {al}", flush=True)
+                wl = W.macrospin_pair(sr, al, T_K=T, n_real=MACROSPIN_REAL)
+                st = streamed_stats(wl, MACROSPIN_REAL, threads)
+                st.update(SR=sr, T=T)
+                out["pairs"].append(st)
+                print(f"  done in {st['oracle_seconds']} s", flush=True)
+            with open(os.path.join(HERE, f"loop_stats_{name}.json"), "w") as f:
+                json.dump(out, f, indent=1)
+            continue
         wl = W.workload(name)
         out = {"_source": "FP64 oracle (oracle/), written by tests/golden/make_loop_stats.py",
                "workload": name, "oracle_sha256": oracle_digest(), "threads": threads, "levels": []}
@@ -92,4 +155,4 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or list(SUBSETS))
+    main(sys.argv[1:] or list(SUBSETS) + list(MACROSPIN))

@@ -102,3 +102,34 @@ def test_fit_recovers_anisotropy_from_its_loop(P):
     print([(h["K"] / v["K"], h["S"]) for h in hist])
     assert abs(vals["K"] / v["K"] - 1) < 2e-2, hist
     assert hist[-1]["err"] < hist[0]["err"] * 1e-2
+
+
+def test_fit_to_an_oracle_loop_with_the_loop_height(P, orc):
+    # The target is a loop of the FP64 oracle: the b = 8 switching rod with
+    # its anisotropy 1.25 times the rule's, 32 realizations, reported in
+    # physical units with an Eq. 13 weight delta = 0.3 instead of 0.511.
+    # Starting from the rule's values, fitting K and delta (delta set from
+    # the remanence) must land on the target's area and coercive field within
+    # one standard error of the target ensemble.
+    import torch
+    from paper_1912_00310_amd.fit import fit_level
+    mat, lvd = switching_level(n_real=32)
+    v = rule_values(P, mat, lvd)
+    lv_t = gk.compile_level(dict(mat, K0=1.25 * mat["K0"]), lvd, 0)
+    seeds = [lvd["seed_base"] + r for r in range(32)]
+    mbar, _ = orc.run_batch(lv_t, seeds, lv_t["n_steps"])
+    ref = orc.ensemble_stats(lv_t, orc.field_schedule_Oe(lv_t), mbar)
+    z = lv_t["hscale"]
+    cM = 1.0 - 0.3 * (1.0 - z)
+    target = (ref["S_sim"] * cM / z, ref["Hc"] / z)
+    se = (ref["S_se"] * cM / z, ref["Hc_se"] / z)
+    mr_t = ref["Mr"] * cM
+    vals, hist = fit_level(mat, lvd, v, target, fit=("K",), hc_weight=target[0] / target[1], steps=8,
+                           units="phys", mr_target=mr_t)
+    last = hist[-1]
+    print("target", target, "+-", se, "fit", [(h["K"] / v["K"], h["S"], h["Hc"], h["delta"]) for h in hist])
+    assert abs(last["S"] - target[0]) <= se[0], (last["S"], target[0], se[0])
+    assert abs(last["Hc"] - target[1]) <= se[1], (last["Hc"], target[1], se[1])
+    assert abs(vals["K"] / (1.25 * v["K"]) - 1) < 0.1, vals["K"] / v["K"]
+    assert abs(vals["delta"] - 0.3) < 0.05, vals["delta"]
+    assert last["Mr"] == pytest.approx(mr_t, rel=1e-9)
