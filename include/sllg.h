@@ -85,6 +85,12 @@ typedef struct {
     double ms_scale;        /* Ms = ms_scale * Ms0 (not rescaled with b); 1 by default   */
     double sr_ref_Oe_per_ns;/* > 0: alpha = alpha_ref * SR / SR_ref for every level      */
     double alpha_ref;
+    int32_t demag;          /* != 0: add the magnetostatic field of the cells, -Ms sum_j
+                               N(r_i - r_j) m_j with N the demagnetising tensor of two
+                               uniformly magnetised cubes (beyond the paper, which folds
+                               shape anisotropy into K); every level then runs on plan 5,
+                               a direct sum over the cells, and may hold at most 1024
+                               cells; sllg_grad refuses such levels                      */
 } sllg_material;
 
 /* One coarse-graining level: a grid and its realizations. */
@@ -240,7 +246,9 @@ int sllg_set_state(sllg_ctx* ctx, int32_t level, int32_t real, const float* host
  * neighbours through device memory each step, 4 = single-cell levels only
  * (the single-macrospin limit): one realization per lane for up to 2^20
  * steps per launch (automatic when every level of the context is a single
- * cell).  All plans give bit-identical states.  Changing the plan is allowed
+ * cell), 5 = with magnetostatics (material demag != 0; the only plan such a
+ * level can use): one workgroup per realization, the field summed directly
+ * over the cells.  Plans 1-4 give bit-identical states.  Changing the plan is allowed
  * between runs.  Returns SLLG_E_INVAL if the plan cannot hold the level
  * (plan 3: more slabs than can be co-resident, or a slab thicker than the
  * workgroup's LDS holds; plan 4: more than one cell). */

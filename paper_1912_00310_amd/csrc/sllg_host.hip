@@ -29,6 +29,7 @@
 #include "sllg_slab.hip"
 #include "sllg_rows2.hip"
 #include "sllg_lanes.hip"
+#include "sllg_demag.hip"
 
 using namespace sllg;
 
@@ -69,7 +70,7 @@ constexpr double kGammaE = 1.76e11;
 constexpr double kGamma0 = kMu0 * kGammaE;
 constexpr double kOe = 1000.0 / (4.0 * kPi);   // A/m per Oe
 
-constexpr int kPlanAuto = 0, kPlanResident = 1, kPlanStream = 2, kPlanSlab = 3, kPlanLanes = 4;
+constexpr int kPlanAuto = 0, kPlanResident = 1, kPlanStream = 2, kPlanSlab = 3, kPlanLanes = 4, kPlanDemag = 5;
 static_assert(kSlabChunk < 2048, "slab exchange tags hold the step of a launch in 11 bits");
 
 // Compiled FP64 constants of one level.
@@ -91,6 +92,7 @@ struct LevelHost {
     int slab_tz;
     int slab0, nslab;     // slab table range
     int64_t xch_off;      // word offset of the level's exchange buffer
+    int64_t demag_off = -1;   // float offset of the demagnetising-tensor table
     int64_t step;         // host view of the step index
 };
 
@@ -138,10 +140,16 @@ constexpr int kResMaxChunks = 32;
 struct Layout {
     size_t levels, insts, accs, steps, status, inst_cnt, launch_cnt, partials, tiles, groups, slots,
         chunks, buf0, buf1, axes, records, ckpt, tape, lam, weights, grads, slabs, xch, spart, islab,
-        total;
+        demag, total;
     int64_t state_floats, axes_floats, rec_doubles, ckpt_floats, tape_floats, lam_floats,
-        max_tiles, max_groups, max_chunks, max_w, ninst_total, max_slabs, xch_words;
+        max_tiles, max_groups, max_chunks, max_w, ninst_total, max_slabs, xch_words, demag_floats;
 };
+
+// Floats of the demagnetising-tensor table of a grid: 8 per cell offset.
+int64_t demag_table_floats(const sllg_level& L)
+{
+    return 8LL * (2 * L.nx - 1) * (2 * L.ny - 1) * (2 * L.nz - 1);
+}
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -244,6 +252,7 @@ struct sllg_ctx {
     uint32_t slab_seq = 0;        // slab launches so far (exchange tags)
     double* d_spart = nullptr;
     int32_t* d_islab = nullptr;   // per instance: first slab (level-relative), then slab count
+    float* d_demag = nullptr;     // demagnetising-tensor tables of the levels (magnetostatics)
     std::vector<SlabDev> h_slabs;
     std::vector<int32_t> h_islab;
     // host mirrors
@@ -312,8 +321,87 @@ int validate(const sllg_material* m, const sllg_level* L, int n)
         if (l.dt_s < 0 || !std::isfinite(l.dt_s)) return fail(SLLG_E_INVAL, "level %d: dt must be >= 0", i);
         if (!(l.cone_deg >= 0) || l.cone_deg >= 90) return fail(SLLG_E_INVAL, "level %d: cone in [0, 90)", i);
         if (l.record_every < 1) return fail(SLLG_E_INVAL, "level %d: record_every must be >= 1", i);
+        if (m->demag && (int64_t)l.nx * l.ny * l.nz > 1024)
+            return fail(SLLG_E_INVAL, "level %d: magnetostatics holds at most 1024 cells per realization", i);
     }
     return SLLG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Demagnetising tensor of two uniformly magnetised cubes of unit edge whose
+// centres are (X, Y, Z) edges apart (Newell, Williams and Dunlop, J. Geophys.
+// Res. 98, 9551 (1993)): N_xx is -1/(4 pi) times the second differences (step
+// 1, weights 1 -2 1) in x, y and z of their function f(x, y, z), N_xy the same
+// of g(x, y, z); the other components permute the arguments.  Long double:
+// the differences cancel to ~r^-3 from terms ~r^2.
+// ---------------------------------------------------------------------------
+using ldbl = long double;
+
+ldbl asinh_ratio(ldbl a, ldbl b2)   // asinh(a / sqrt(b2)) for a >= 0, b2 > 0
+{
+    return std::log((a + std::sqrt(a * a + b2)) / std::sqrt(b2));
+}
+
+ldbl nwl_f(ldbl x, ldbl y, ldbl z)
+{
+    x = std::fabs(x);
+    y = std::fabs(y);
+    z = std::fabs(z);
+    const ldbl xx = x * x, yy = y * y, zz = z * z, R = std::sqrt(xx + yy + zz);
+    ldbl v = (2 * xx - yy - zz) * R / 6;
+    if (y > 0 && xx + zz > 0) v += y * (zz - xx) / 2 * asinh_ratio(y, xx + zz);
+    if (z > 0 && xx + yy > 0) v += z * (yy - xx) / 2 * asinh_ratio(z, xx + yy);
+    if (x > 0 && y > 0 && z > 0) v -= x * y * z * std::atan2(y * z, x * R);
+    return v;
+}
+
+ldbl nwl_g(ldbl x, ldbl y, ldbl z)
+{
+    const ldbl sign = (x < 0) == (y < 0) ? 1 : -1;   // odd in x and in y
+    x = std::fabs(x);
+    y = std::fabs(y);
+    z = std::fabs(z);
+    const ldbl xx = x * x, yy = y * y, zz = z * z, R = std::sqrt(xx + yy + zz);
+    ldbl v = -x * y * R / 3;
+    if (x > 0 && y > 0) {
+        if (z > 0) {
+            v += x * y * z * asinh_ratio(z, xx + yy);
+            v -= z * zz / 6 * std::atan2(x * y, z * R);
+            v -= z * yy / 2 * std::atan2(x * z, y * R);
+            v -= z * xx / 2 * std::atan2(y * z, x * R);
+        }
+        v += y * (3 * zz - yy) / 6 * asinh_ratio(x, yy + zz);
+        v += x * (3 * zz - xx) / 6 * asinh_ratio(y, xx + zz);
+    }
+    return sign * v;
+}
+
+template <class F>
+ldbl second_differences(F fn, ldbl X, ldbl Y, ldbl Z)
+{
+    auto dz = [&](ldbl x, ldbl y) { return fn(x, y, Z + 1) - 2 * fn(x, y, Z) + fn(x, y, Z - 1); };
+    auto dy = [&](ldbl x) { return dz(x, Y + 1) - 2 * dz(x, Y) + dz(x, Y - 1); };
+    return -(dy(X + 1) - 2 * dy(X) + dy(X - 1)) / (4 * (ldbl)kPi);
+}
+
+// -Ms N for every offset of an nx x ny x nz grid, 8 floats per offset
+// (xx yy zz xy | xz yz 0 0), offset index ((dz + nz-1)(2ny-1) + dy + ny-1)(2nx-1) + dx + nx-1.
+void demag_table(const sllg_level& L, double Ms, std::vector<float>& out)
+{
+    const int wx = 2 * L.nx - 1, wy = 2 * L.ny - 1, wz = 2 * L.nz - 1;
+    out.assign((size_t)8 * wx * wy * wz, 0.0f);
+    for (int k = 0; k < wz; ++k)
+        for (int j = 0; j < wy; ++j)
+            for (int i = 0; i < wx; ++i) {
+                const ldbl X = i - L.nx + 1, Y = j - L.ny + 1, Z = k - L.nz + 1;
+                float* o = out.data() + 8 * (((size_t)k * wy + j) * wx + i);
+                o[0] = (float)(-Ms * second_differences(nwl_f, X, Y, Z));
+                o[1] = (float)(-Ms * second_differences(nwl_f, Y, X, Z));
+                o[2] = (float)(-Ms * second_differences(nwl_f, Z, Y, X));
+                o[3] = (float)(-Ms * second_differences(nwl_g, X, Y, Z));
+                o[4] = (float)(-Ms * second_differences(nwl_g, X, Z, Y));
+                o[5] = (float)(-Ms * second_differences(nwl_g, Y, Z, X));
+            }
 }
 
 void compile_level(const sllg_material& m, const sllg_level& in, LevelHost& o)
@@ -381,6 +469,7 @@ LevelDev to_dev(const sllg_material& m, const LevelHost& h, int tag)
     d.has_axes = h.axes_off >= 0 ? 1 : 0;
     d.axes_off = h.axes_off >= 0 ? h.axes_off : 0;
     d.n_rec = h.n_rec;
+    d.demag_off = h.demag_off >= 0 ? h.demag_off : 0;
     return d;
 }
 
@@ -416,8 +505,8 @@ Layout make_layout(const sllg_material& m, const std::vector<LevelHost>& lv, int
             L.max_slabs += ns;
             L.xch_words += 2 * ns * 12 * (int64_t)h.in.nx * h.in.ny;
         }
+        if (m.demag) L.demag_floats += demag_table_floats(h.in);
     }
-    (void)m;
     L.ninst_total = ninst;
     L.state_floats = state;
     L.axes_floats = axes;
@@ -460,6 +549,7 @@ Layout make_layout(const sllg_material& m, const std::vector<LevelHost>& lv, int
     L.xch = take(sizeof(uint64_t) * L.xch_words);
     L.spart = take(sizeof(double) * L.max_slabs * kSlabChunk);
     L.islab = take(sizeof(int32_t) * 2 * ninst);
+    L.demag = take(sizeof(float) * L.demag_floats);
     L.total = o;
     return L;
 }
@@ -813,6 +903,33 @@ hipError_t dispatch_lanes(sllg_ctx* C, int l0, int l1, int64_t n0, int64_t ns)
     return hipGetLastError();
 }
 
+// Levels with magnetostatics: one workgroup per realization, ns steps.
+template <int NT>
+hipError_t launch_demag_t(sllg_ctx* C, int level, int64_t n0, int64_t ns)
+{
+    const LevelHost& h = C->lv[level];
+    hipLaunchKernelGGL(k_demag<NT>, dim3((unsigned)h.ninst), dim3(NT), 0, C->stream, C->d_insts, h.inst0,
+                       C->d_levels, C->d_buf0, C->d_buf1, C->d_axes, C->d_demag, C->d_records, C->d_accs,
+                       C->d_ckpt, C->ckpt_every, n0, ns, C->d_status);
+    return hipGetLastError();
+}
+
+int demag_threads(const LevelHost& h)
+{
+    return h.ncell <= 64 ? 64 : h.ncell <= 128 ? 128 : h.ncell <= 256 ? 256 : h.ncell <= 512 ? 512 : 1024;
+}
+
+hipError_t dispatch_demag(sllg_ctx* C, int level, int64_t n0, int64_t ns)
+{
+    switch (demag_threads(C->lv[level])) {
+    case 64: return launch_demag_t<64>(C, level, n0, ns);
+    case 128: return launch_demag_t<128>(C, level, n0, ns);
+    case 256: return launch_demag_t<256>(C, level, n0, ns);
+    case 512: return launch_demag_t<512>(C, level, n0, ns);
+    default: return launch_demag_t<1024>(C, level, n0, ns);
+    }
+}
+
 template <int TX, int TY, int PZ>
 hipError_t launch_stream_t(sllg_ctx* C, int level)
 {
@@ -1146,6 +1263,31 @@ int run_steps(sllg_ctx* C, int64_t nsteps)
                 C->timed_cells = h.ncell * h.ninst;
             }
             HIP_OK(fold_slabs(C, l, h.step, ns));
+            h.step += ns;
+            k -= ns;
+        }
+    }
+    // levels with magnetostatics: launches of at most 4096 steps
+    for (int l = 0; l < (int)C->lv.size(); ++l) {
+        LevelHost& h = C->lv[l];
+        if (h.plan != kPlanDemag) continue;
+        int64_t k = std::min(nsteps, h.n_steps - h.step);
+        while (k > 0) {
+            const int64_t ns = std::min<int64_t>(k, 4096);
+            const bool time_this = C->timing > 0 && (C->unit_counter++ % C->timing) == 0;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (time_this) {
+                e0 = next_event(C);
+                e1 = next_event(C);
+                if (!e0 || !e1) return fail(SLLG_E_HIP, "event pool");
+                HIP_OK(hipEventRecord(e0, C->stream));
+            }
+            HIP_OK(dispatch_demag(C, l, h.step, ns));
+            if (time_this) {
+                HIP_OK(hipEventRecord(e1, C->stream));
+                C->ev_launches.push_back(1);
+                C->timed_cells = h.ncell * h.ninst * ns;
+            }
             h.step += ns;
             k -= ns;
         }
@@ -1613,6 +1755,7 @@ int init_impl(const sllg_material* mat, const sllg_level* levels, int32_t n_leve
     C->d_xch = (uint64_t*)(C->ws + L.xch);
     C->d_spart = (double*)(C->ws + L.spart);
     C->d_islab = (int32_t*)(C->ws + L.islab);
+    C->d_demag = (float*)(C->ws + L.demag);
     C->h_islab.assign(2 * (size_t)L.ninst_total, 0);
     int dev = 0;
     hipDeviceProp_t prop;
@@ -1628,8 +1771,27 @@ int init_impl(const sllg_material* mat, const sllg_level* levels, int32_t n_leve
     for (const LevelHost& h : C->lv) all_single = all_single && h.ncell == 1;
     for (int i = 0; i < n_levels; ++i) {
         LevelHost& h = C->lv[i];
-        h.plan = all_single ? kPlanLanes : resident_fits(h, C->max_lds) ? kPlanResident : kPlanStream;
+        h.plan = mat->demag    ? kPlanDemag
+                 : all_single ? kPlanLanes
+                 : resident_fits(h, C->max_lds) ? kPlanResident
+                                                : kPlanStream;
         if (h.plan == kPlanStream) default_stream_shape(C, h);
+    }
+    // tensor tables of the magnetostatic field (host, long double), once
+    if (mat->demag) {
+        int64_t off = 0;
+        for (int i = 0; i < n_levels; ++i) {
+            LevelHost& h = C->lv[i];
+            std::vector<float> tab;
+            demag_table(h.in, h.Ms, tab);
+            h.demag_off = off;
+            if (hipMemcpy(C->d_demag + off, tab.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice) !=
+                hipSuccess) {
+                delete C;
+                return fail(SLLG_E_HIP, "demagnetising-tensor upload failed");
+            }
+            off += (int64_t)tab.size();
+        }
     }
     rc = replan(C);
     if (rc) {
@@ -1893,6 +2055,8 @@ int sllg_level_kernel(const sllg_ctx* C, int32_t level, char* name, int32_t cap)
                  h.slab_tz, kSlabChunk);
     } else if (h.plan == kPlanLanes) {
         snprintf(buf, sizeof(buf), "k_lanes<%d>", kLanesThreads);
+    } else if (h.plan == kPlanDemag) {
+        snprintf(buf, sizeof(buf), "k_demag<%d>", demag_threads(h));
     } else {
         for (const auto& rs : C->res_sets)
             if (std::find(rs.levels.begin(), rs.levels.end(), level) != rs.levels.end())
@@ -1947,6 +2111,15 @@ int sllg_set_plan(sllg_ctx* C, int32_t level, int32_t plan)
 {
     if (!C || level < 0 || level >= (int)C->lv.size()) return fail(SLLG_E_INVAL, "bad level");
     LevelHost& h = C->lv[level];
+    // magnetostatics has one plan, and that plan needs the field tables
+    if (C->mat.demag && plan != kPlanAuto && plan != kPlanDemag)
+        return fail(SLLG_E_INVAL, "a level with magnetostatics runs on plan 5 only");
+    if (!C->mat.demag && plan == kPlanDemag) return fail(SLLG_E_INVAL, "plan 5 needs material demag != 0");
+    if (C->mat.demag) {
+        h.forced = plan == kPlanDemag;
+        h.plan = kPlanDemag;
+        return replan(C);
+    }
     if (plan == kPlanAuto) {
         h.forced = 0;
         bool all_single = true;
@@ -2006,6 +2179,7 @@ int sllg_set_slab_shape(sllg_ctx* C, int32_t level, int32_t kind, int32_t thread
                         int32_t planes)
 {
     if (!C || level < 0 || level >= (int)C->lv.size()) return fail(SLLG_E_INVAL, "bad level");
+    if (C->mat.demag) return fail(SLLG_E_INVAL, "a level with magnetostatics runs on plan 5 only");
     LevelHost& h = C->lv[level];
     if (!slab_eligible(h.in)) return fail(SLLG_E_INVAL, "level %d cannot use slabs (nx*ny <= 1024, nz >= 4)", level);
     int ki = -1;
@@ -2038,6 +2212,7 @@ int sllg_set_stream_shape(sllg_ctx* C, int32_t level, int32_t kind, int32_t a, i
                           int32_t planes)
 {
     if (!C || level < 0 || level >= (int)C->lv.size()) return fail(SLLG_E_INVAL, "bad level");
+    if (C->mat.demag) return fail(SLLG_E_INVAL, "a level with magnetostatics runs on plan 5 only");
     LevelHost& h = C->lv[level];
     int si = -1;
     for (int i = 0; i < kNumShapes; ++i)
@@ -2143,6 +2318,7 @@ int sllg_grad(sllg_ctx* C, int32_t level, double g_area[4], double g_hc[4])
     if (h.in.record_every != 1) return fail(SLLG_E_STATE, "sllg_grad needs record_every == 1");
     if (h.step != h.n_steps) return fail(SLLG_E_STATE, "run the whole sweep before sllg_grad");
     if (h.ncell > 1024) return fail(SLLG_E_INVAL, "the adjoint holds at most 1024 cells per realization");
+    if (C->mat.demag) return fail(SLLG_E_STATE, "the adjoint has no magnetostatic term");
     int rc = check_status(C);
     if (rc) return rc;
     const int64_t NS = h.n_steps, R = h.ninst;

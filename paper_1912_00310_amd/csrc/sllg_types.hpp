@@ -30,6 +30,7 @@ struct LevelDev {
     int32_t has_axes;        // per-cell axes stored at axes_off
     int64_t axes_off;        // float offset of the ux plane in the axes array
     int64_t n_rec;           // recorded points per instance
+    int64_t demag_off;       // float offset of the demagnetising-tensor table (magnetostatics)
 };
 
 // One instance = one realization of one level.

@@ -19,7 +19,7 @@ SLLG_OK = 0
 ERRORS = {-1: "SLLG_E_INVAL", -2: "SLLG_E_WORKSPACE", -3: "SLLG_E_CAPACITY",
           -4: "SLLG_E_STATE", -5: "SLLG_E_HIP", -6: "SLLG_E_NUMERIC"}
 WAVES = {"triangle": 0, "cosine": 1, "constant": 2}
-PLAN_AUTO, PLAN_RESIDENT, PLAN_STREAM, PLAN_SLAB, PLAN_LANES = 0, 1, 2, 3, 4
+PLAN_AUTO, PLAN_RESIDENT, PLAN_STREAM, PLAN_SLAB, PLAN_LANES, PLAN_DEMAG = 0, 1, 2, 3, 4, 5
 OPT_NO_TUNE, OPT_NO_SLAB, OPT_NO_GRAPH, OPT_VERBOSE = 1, 2, 4, 8
 
 
@@ -36,7 +36,7 @@ class Material(C.Structure):
         ("easy_axis", C.c_double * 3), ("Hmax_Oe", C.c_double), ("sweep_Oe_per_ns", C.c_double),
         ("wave", C.c_int32), ("n_cycles", C.c_int32), ("scale_AK", C.c_int32),
         ("scale_H", C.c_int32), ("ms_scale", C.c_double), ("sr_ref_Oe_per_ns", C.c_double),
-        ("alpha_ref", C.c_double),
+        ("alpha_ref", C.c_double), ("demag", C.c_int32),
     ]
 
 
@@ -139,6 +139,7 @@ def material_struct(m: dict) -> Material:
     s.scale_AK, s.scale_H = int(bool(m.get("scale_AK", True))), int(bool(m.get("scale_H", True)))
     s.ms_scale = m.get("ms_scale", 1.0)
     s.sr_ref_Oe_per_ns, s.alpha_ref = m.get("sr_ref_Oe_per_ns", 0.0), m.get("alpha_ref", 0.0)
+    s.demag = int(bool(m.get("demag", False)))
     return s
 
 

@@ -56,6 +56,7 @@ BASE_MATERIAL = dict(
     ms_scale=1.0,
     sr_ref_Oe_per_ns=0.0,   # >0 switches on alpha = alpha_ref*SR/SR_ref
     alpha_ref=0.0,
+    demag=False,            # magnetostatic field of the cells (beyond the paper)
 )
 
 

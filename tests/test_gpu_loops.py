@@ -206,3 +206,36 @@ def test_numeric_blowup_is_reported(P):
     sim.reset()
     sim.synchronize()
     sim.close()
+
+
+def _golden(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"loop_stats_{name}.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+def test_multilevel_whole_loops_against_the_oracle(P):
+    # the four-level batch (1024 instances, b = 1 streamed) over its whole
+    # 8e5-step sweep; for every level the realizations the FP64 oracle ran
+    # (seeds 1..8, 1..16, 1..32, 1..32: tests/golden/make_loop_stats.py)
+    # give loop areas within two standard errors of the oracle's, and, like
+    # the oracle's, loops without a coercive crossing (alpha = 400 by the
+    # SR/alpha rule: the moments lag the 1e3 Oe/ns sweep)
+    g = _golden("multilevel_ens256")
+    wl = W.workload("multilevel_ens256")
+    sim = P.Sim(wl["material"], wl["levels"])
+    sim.run_sweep()
+    for l, ref in enumerate(g["levels"]):
+        k = len(ref["seeds"])
+        S = np.array([sim.loop(l, r)[2]["S_sim"] for r in range(k)])
+        se = S.std(ddof=1) / math.sqrt(k)
+        mean_ref = float(np.mean(ref["S"]))
+        s = math.sqrt(se ** 2 + ref["S_se"] ** 2)
+        print(f"level {l}: S {S.mean():.3f} +- {se:.3f} Oe, oracle {mean_ref:.3f} +- {ref['S_se']:.3f} Oe")
+        assert abs(S.mean() - mean_ref) <= 2 * s, (l, S.mean(), mean_ref, s)
+        st = sim.loop(l, -1)[2]
+        assert ref["mean_loop"]["Hc"] is None and math.isnan(st["Hc_sim"])
+        assert st["n_cross_desc"] == 0 and st["n_cross_asc"] == 0
+    sim.close()

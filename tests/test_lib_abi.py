@@ -99,3 +99,16 @@ def test_options_and_null_contexts_rejected(L):
     assert lib.sllg_set_options(0) == 0
     assert lib.sllg_sync(None) == -1
     assert lib.sllg_set_spin_limit(None, 0) == -1
+
+
+def test_demag_level_size_limit(L):
+    wl = W.workload("rod_b4_single")
+    wl["material"]["demag"] = True
+    wl["levels"][0].update(nx=8, ny=8, nz=17)       # 1088 cells
+    m = L.material_struct(wl["material"])
+    lv = L.levels_struct(wl["levels"])
+    assert L.lib().sllg_workspace_bytes(C.byref(m), lv, 1, 0) == 0
+    assert b"1024 cells" in L.lib().sllg_last_error()
+    wl["levels"][0].update(nz=16)                   # 1024 cells
+    lv = L.levels_struct(wl["levels"])
+    assert L.lib().sllg_workspace_bytes(C.byref(m), lv, 1, 0) > 0
