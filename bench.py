@@ -23,6 +23,13 @@ Legs in the same line (each a fixed amount of work, independent of --steps):
                          (grad_over_forward)
   block_b2_cone10_z1024  the block at 128x128x1024 (state and axes beyond the
                          256 MB Infinity Cache), a 2000-step window
+  macrospin_sr2p5_ens256 the single-macrospin limit (one cell of the rod's
+                         volume) at SR = 2.5 Oe/ns, alpha = 1 (SR/alpha =
+                         2.5 Oe/ns, Fig. 4): 256 realizations, one per lane,
+                         8e5 steps of 1 ps
+  rod_b4_demag64         the 2x6x14 b = 4 rod of the adjoint workload with the
+                         magnetostatic field (beyond the paper), 64
+                         realizations, 4e4 steps
 
 Shape pins for counter runs: --stream-shape kind,a,b,c,planes and
 --slab-shape kind,threads,cells,planes switch the tuners off and set the
@@ -45,7 +52,8 @@ if ROOT not in sys.path:
 
 METRIC = "sLLG cell-updates/s & loops/s at 1 GPU (% HBM roofline); batched & adjoint vs plain"
 HEADLINE = "block_b2_cone10"
-LEGS = ("rod_b1_ens8", "multilevel_ens256", "rod_b4_adjoint64", "block_b2_cone10_z1024")
+LEGS = ("rod_b1_ens8", "multilevel_ens256", "rod_b4_adjoint64", "block_b2_cone10_z1024",
+        "macrospin_sr2p5_ens256", "rod_b4_demag64")
 
 # Algorithmic work of one cell-update (one Heun step of one cell).
 # HBM: m_n in and m_{n+1} out (12 + 12 bytes); stored per-cell easy axes add
@@ -98,6 +106,13 @@ def workload(name):
         wl = W.workload("block_b2_cone10")
         wl["levels"][0]["nz"] = 1024
         return wl
+    if name == "macrospin_sr2p5_ens256":
+        return W.macrospin_pair(2.5, 1.0, T_K=310.0, n_real=256)
+    if name == "rod_b4_demag64":
+        wl = W.workload("rod_b4_adjoint64")
+        wl["material"]["demag"] = True
+        wl["ckpt_every"] = 0
+        return wl
     return W.workload(name)
 
 
@@ -122,7 +137,7 @@ def dominant_kernel(sim, n_levels):
     """Kernel the library times (streamed if a level is streamed, else slab,
     else resident) and its family."""
     kernels = [sim.kernel_name(l) for l in range(n_levels)]
-    fam = next((f for f in ("k_stream", "k_rows", "k_slab", "k_resident", "k_lanes")
+    fam = next((f for f in ("k_stream", "k_rows", "k_slab", "k_resident", "k_lanes", "k_demag")
                 if any(k.startswith(f) for k in kernels)), "none")
     if fam == "k_rows" and any(k.startswith("k_stream") for k in kernels):
         fam = "k_stream"
@@ -144,9 +159,14 @@ def roofline(sim, wl, name, k_ms, k_n, k_cells):
     per_launch = k_cells * spl        # cell-updates per launch
     has_axes = any(l.get("cone_deg", 0) > 0 for l in levels)
     bpc = BYTES_PER_CELL_UPDATE + (BYTES_AXES if has_axes else 0)
+    fpc = FLOPS_PER_CELL_UPDATE
+    if fam == "k_demag":
+        # the magnetostatic field: a 3x3 tensor times m_j (9 FMA = 18 flops)
+        # for every cell j, in both Heun stages
+        fpc += 36 * max(l["nx"] * l["ny"] * l["nz"] for l in levels)
     s = launch_ms * 1e-3
     gbs = per_launch * bpc / s / 1e9
-    tflops = per_launch * FLOPS_PER_CELL_UPDATE / s / 1e12
+    tflops = per_launch * fpc / s / 1e12
     valu = per_launch * VALU_OPS_PER_CELL_UPDATE / s / 1e12
     traffic = measured_traffic(dom, name)
     # streamed kernels move the state through HBM every step (the HBM
@@ -162,6 +182,7 @@ def roofline(sim, wl, name, k_ms, k_n, k_cells):
         "kernel": dom, "mean_launch_ms": launch_ms, "steps_per_launch": spl,
         "launches_timed": k_n // spl if spl > 1 else k_n, "cell_updates_per_launch": per_launch,
         "bytes_per_cell_update": bpc, "algorithmic_bytes_per_launch": per_launch * bpc,
+        "flops_per_cell_update": fpc,
         "hbm_GBps": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4),
         "fp32_TFLOPs": round(tflops, 3), "fp32_frac": round(tflops / PEAK_FP32_TFLOPS, 4),
         "valu_issue_frac": round(valu / PEAK_VALU_ISSUE_TOPS, 4),
@@ -308,6 +329,8 @@ def run_leg(name):
         r = run_workload(name, steps=3, warmup=1)
     elif name == "block_b2_cone10_z1024":
         r = run_workload(name, steps=2, warmup=1)
+    elif name in ("macrospin_sr2p5_ens256", "rod_b4_demag64"):
+        r = run_workload(name, steps=2, warmup=1)
     else:
         raise ValueError(f"unknown leg {name}")
     r.pop("steps", None)
@@ -315,14 +338,27 @@ def run_leg(name):
     return r
 
 
-def source_digest():
-    """SHA-256 over the kernel sources (csrc/*.hip, *.hpp, sorted by name)."""
-    d = os.path.join(ROOT, "paper_1912_00310_amd", "csrc")
+# The source files a kernel's device code is compiled from (besides the
+# shared per-cell header, the shared types and the build flags).
+KERNEL_SOURCES = {
+    "k_rows2": "sllg_rows2.hip", "k_rows": "sllg_rows.hip", "k_stream": "sllg_kernels.hip",
+    "k_resident": "sllg_kernels.hip", "k_slab": "sllg_slab.hip", "k_slab2": "sllg_slab.hip",
+    "k_lanes": "sllg_lanes.hip", "k_demag": "sllg_demag.hip", "k_adjoint": "sllg_adjoint.hip",
+}
+
+
+def source_digest(kernel):
+    """SHA-256 over the sources of one kernel's device code: its own file,
+    the per-cell header and the shared types (csrc/) and the build script
+    (compiler flags), in that order."""
+    fam = kernel.split("<")[0].split()[0]
+    pkg = os.path.join(ROOT, "paper_1912_00310_amd")
+    files = [os.path.join(pkg, "build_lib.py")] + [
+        os.path.join(pkg, "csrc", n) for n in ("sllg_device.hpp", "sllg_types.hpp", KERNEL_SOURCES[fam])]
     h = hashlib.sha256()
-    for n in sorted(os.listdir(d)):
-        if n.endswith((".hip", ".hpp")):
-            with open(os.path.join(d, n), "rb") as f:
-                h.update(n.encode() + b"\0" + f.read())
+    for path in files:
+        with open(path, "rb") as f:
+            h.update(os.path.basename(path).encode() + b"\0" + f.read())
     return h.hexdigest()
 
 
@@ -351,7 +387,10 @@ def measured_traffic(kernel, workload_name):
             if ":" in line:
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("source_sha256") != source_digest():
+    try:
+        if kv.get("source_sha256") != source_digest(kernel):
+            return None
+    except KeyError:
         return None
     if "<" in kernel and kernel_instance(kv.get("kernel", "")) != kernel_instance(kernel):
         return None

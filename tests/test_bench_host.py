@@ -1,6 +1,6 @@
 """Host-side pieces of bench.py: the committed HBM-traffic summaries are found
-under the dominant kernel's template name and are used only while the kernel
-sources are the ones they were measured on."""
+under the dominant kernel's template name and are used only while the sources
+of that kernel's device code are the ones they were measured on."""
 import glob
 import os
 
@@ -30,7 +30,7 @@ def test_traffic_summaries_are_found_by_kernel_template_name():
         inst = bench.kernel_instance(kv["kernel"]) + "> tz 7"
         got = bench.measured_traffic(inst, workload)
         assert bench.measured_traffic(kernel + "<1,1> tz 7", workload) is None   # another instantiation
-        if kv["source_sha256"] == bench.source_digest():
+        if kv["source_sha256"] == bench.source_digest(kv["kernel"]):
             assert got == int(float(kv["hbm_bytes_per_launch"]))
         else:
             assert got is None
@@ -50,3 +50,9 @@ def test_kernel_instance_names():
 def test_unknown_kernel_or_workload_has_no_traffic():
     assert bench.measured_traffic("k_nonexistent", "rod_b1_ens8") is None
     assert bench.measured_traffic("k_slab", "no_such_workload") is None
+
+
+def test_source_digest_covers_only_the_kernels_own_sources():
+    a = bench.source_digest("k_rows2<1024,1> tz 43")
+    assert a == bench.source_digest("k_rows2")
+    assert a != bench.source_digest("k_slab<1024,1>")
