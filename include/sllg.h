@@ -192,10 +192,12 @@ int sllg_loop(sllg_ctx* ctx, int32_t level, int32_t real, double* H_Oe, double* 
  * Hc_sim of the ensemble-mean loop (g_hc) with respect to
  * (K, A, alpha, ms_scale), K and A being the level's simulated values.
  * Needs a completed sweep run with ckpt_every > 0 and record_every == 1,
- * and a level of at most 1024 cells.  One segment of ckpt_every steps has
- * its applied field and loss weights in LDS: ckpt_every may be at most 3305
- * for levels of 513-1024 cells (11000 and more for smaller ones); beyond
- * that SLLG_E_INVAL.  g_hc is NaN when the mean loop has no crossing on a
+ * and a level of at most 1536 cells (one workgroup per realization; two
+ * cells per thread above 1024), without magnetostatics.  One segment of
+ * ckpt_every steps has its applied field and loss weights in LDS: the
+ * largest ckpt_every allowed shrinks with the level (11065 up to 256 cells,
+ * 9501 up to 512, 5351 up to 1024, 1282 up to 1536); beyond that
+ * SLLG_E_INVAL.  g_hc is NaN when the mean loop has no crossing on a
  * branch.  FP64 accumulation; synchronises the stream. */
 int sllg_grad(sllg_ctx* ctx, int32_t level, double g_area[4], double g_hc[4]);
 

@@ -1,7 +1,7 @@
 // Discrete adjoint of the Heun stochastic-LLG step under fixed noise.
 //
 // One workgroup per realization, one cell per thread (levels up to 1024
-// cells).  The sweep is replayed backwards in segments of ckpt_every steps:
+// cells), or two cells per thread for levels of up to 1536 cells.  The sweep is replayed backwards in segments of ckpt_every steps:
 // each segment is first recomputed forward from its checkpoint with the same
 // per-cell arithmetic as the forward kernels (so the replay is bit-identical)
 // and taped to global memory (m_n, m', xi per cell and step); then the
@@ -56,26 +56,33 @@ __device__ __forceinline__ V3 rhs_dm_T(float g1, float ag1, V3 m, V3 H, V3 v)
 
 // Workgroups of up to 256 cells get NT more threads: thread NT + i draws the
 // thermal field of cell i for the next replay step into LDS while the cell
-// threads step the current one.
-template <int NT>
-constexpr int kAdjThreads = NT <= 256 ? 2 * NT : NT;
+// threads step the current one.  With KC > 1 every thread owns the cells
+// tid + k NT (k < KC) and draws their noise itself (levels of more than 1024
+// cells, up to NT KC).
+template <int NT, int KC>
+constexpr bool kAdjNoiseThreads = KC == 1 && NT <= 256;
+template <int NT, int KC = 1>
+constexpr int kAdjThreads = kAdjNoiseThreads<NT, KC> ? 2 * NT : NT;
 
-template <int NT>
-__global__ __launch_bounds__(kAdjThreads<NT>) void k_adjoint(const InstDev* __restrict__ insts, int inst0,
-                                                const LevelDev* __restrict__ levels,
-                                                const float* __restrict__ axes,
-                                                const float* __restrict__ ckpt, int ckpt_every,
-                                                float* __restrict__ tape, const double* __restrict__ w,
-                                                double* __restrict__ grads)
+template <int NT, int KC>
+__global__ __launch_bounds__((kAdjThreads<NT, KC>)) void k_adjoint(const InstDev* __restrict__ insts, int inst0,
+                                                                 const LevelDev* __restrict__ levels,
+                                                                 const float* __restrict__ axes,
+                                                                 const float* __restrict__ ckpt, int ckpt_every,
+                                                                 float* __restrict__ tape,
+                                                                 const double* __restrict__ w,
+                                                                 double* __restrict__ grads)
 {
+    constexpr int NC = NT * KC;   // cells a workgroup holds
+    constexpr bool NP = kAdjNoiseThreads<NT, KC>;
     // m_n and m' by step parity: the replay uses parity 0; the reverse walk
     // writes the tape of step n - 1 into the other parity while step n works,
     // so a reverse step needs two barriers
-    __shared__ float AA[2][3][NT];
-    __shared__ float BB[2][3][NT];
-    __shared__ float HB[2][2][3][NT];   // H'-bar, H-bar per loss
+    __shared__ float AA[2][3][NC];
+    __shared__ float BB[2][3][NC];
+    __shared__ float HB[2][2][3][NC];   // H'-bar, H-bar per loss
     __shared__ double red[NT / 64][10];
-    __shared__ float XI[2][3][NT];      // replay noise by step parity (noise threads)
+    __shared__ float XI[2][3][NP ? NT : 1];   // replay noise by step parity (noise threads)
     // per segment: the applied field of steps nA .. nB and the loss weights
     // of steps nA .. nB divided by N (FP32, dynamic, ckpt_every + 1 of each)
     extern __shared__ float seg_tab[];
@@ -84,17 +91,15 @@ __global__ __launch_bounds__(kAdjThreads<NT>) void k_adjoint(const InstDev* __re
     const InstDev I = insts[inst];
     const LevelDev& L = levels[I.level];
     const int N = L.ncell, nx = L.nx, ny = L.ny, nz = L.nz;
-    constexpr bool NP = kAdjThreads<NT> > NT;
     const bool noise_thread = NP && static_cast<int>(threadIdx.x) >= NT;
-    const int i = noise_thread ? static_cast<int>(threadIdx.x) - NT : static_cast<int>(threadIdx.x);
-    const bool on = i < N && !noise_thread;
-    const bool draws = noise_thread && i < N;
+    const int t = noise_thread ? static_cast<int>(threadIdx.x) - NT : static_cast<int>(threadIdx.x);
+    const bool draws = noise_thread && t < N;
     auto draw = [&](int64_t n) {
         const V3 xi = gauss3(philox_cell(I.seed, static_cast<uint32_t>(L.level_tag), kTagNoise,
-                                         static_cast<uint32_t>(i), static_cast<uint64_t>(n)));
-        XI[n & 1][0][i] = xi.x;
-        XI[n & 1][1][i] = xi.y;
-        XI[n & 1][2][i] = xi.z;
+                                         static_cast<uint32_t>(t), static_cast<uint64_t>(n)));
+        XI[n & 1][0][t] = xi.x;
+        XI[n & 1][1][t] = xi.y;
+        XI[n & 1][2][t] = xi.z;
     };
     const int64_t NS = L.n_steps;
     const int64_t K = ckpt_every;
@@ -117,63 +122,82 @@ __global__ __launch_bounds__(kAdjThreads<NT>) void k_adjoint(const InstDev* __re
     Lc.dt = dt;
     Lc.half_dt = half_dt;
 
-    int ixm = i, ixp = i, iym = i, iyp = i, izm = i, izp = i;
-    V3 u = V3{L.ux, L.uy, L.uz};
-    if (on) {
-        const int x = i % nx, y = (i / nx) % ny, z = i / (nx * ny);
-        ixm = x > 0 ? i - 1 : i;
-        ixp = x < nx - 1 ? i + 1 : i;
-        iym = y > 0 ? i - nx : i;
-        iyp = y < ny - 1 ? i + nx : i;
-        izm = z > 0 ? i - nx * ny : i;
-        izp = z < nz - 1 ? i + nx * ny : i;
-        if (L.has_axes) {
-            const float* a = axes + L.axes_off;
-            u = V3{a[i], a[N + i], a[2 * N + i]};
+    // the thread's cells
+    int ci[KC], ixm[KC], ixp[KC], iym[KC], iyp[KC], izm[KC], izp[KC];
+    bool on[KC];
+    V3 u[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        const int i = t + k * NT;
+        ci[k] = i;
+        on[k] = i < N && !noise_thread;
+        ixm[k] = ixp[k] = iym[k] = iyp[k] = izm[k] = izp[k] = i;
+        u[k] = V3{L.ux, L.uy, L.uz};
+        if (on[k]) {
+            const int x = i % nx, y = (i / nx) % ny, z = i / (nx * ny);
+            ixm[k] = x > 0 ? i - 1 : i;
+            ixp[k] = x < nx - 1 ? i + 1 : i;
+            iym[k] = y > 0 ? i - nx : i;
+            iyp[k] = y < ny - 1 ? i + nx : i;
+            izm[k] = z > 0 ? i - nx * ny : i;
+            izp[k] = z < nz - 1 ? i + nx * ny : i;
+            if (L.has_axes) {
+                const float* a = axes + L.axes_off;
+                u[k] = V3{a[i], a[N + i], a[2 * N + i]};
+            }
         }
     }
-    auto nb = [&](float (*S)[NT], V3 m) {
-        return nb_sum(m, v3(S[0][ixm], S[1][ixm], S[2][ixm]), v3(S[0][ixp], S[1][ixp], S[2][ixp]),
-                      v3(S[0][iym], S[1][iym], S[2][iym]), v3(S[0][iyp], S[1][iyp], S[2][iyp]),
-                      v3(S[0][izm], S[1][izm], S[2][izm]), v3(S[0][izp], S[1][izp], S[2][izp]));
+    auto nb = [&](float (*S)[NC], V3 m, int k) {
+        return nb_sum(m, v3(S[0][ixm[k]], S[1][ixm[k]], S[2][ixm[k]]), v3(S[0][ixp[k]], S[1][ixp[k]], S[2][ixp[k]]),
+                      v3(S[0][iym[k]], S[1][iym[k]], S[2][iym[k]]), v3(S[0][iyp[k]], S[1][iyp[k]], S[2][iyp[k]]),
+                      v3(S[0][izm[k]], S[1][izm[k]], S[2][izm[k]]), v3(S[0][izp[k]], S[1][izp[k]], S[2][izp[k]]));
     };
-    auto put = [&](float (*S)[NT], V3 v) {
+    auto put = [&](float (*S)[NC], int i, V3 v) {
         S[0][i] = v.x;
         S[1][i] = v.y;
         S[2][i] = v.z;
     };
 
-    V3 lam[2];
-    for (int l = 0; l < 2; ++l) lam[l] = V3{0.0f, 0.0f, static_cast<float>(w[l * (NS + 1) + NS] / N)};
+    V3 lam[KC][2];
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+        for (int l = 0; l < 2; ++l) lam[k][l] = V3{0.0f, 0.0f, static_cast<float>(w[l * (NS + 1) + NS] / N)};
     double g[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
 
     for (int64_t seg = nseg - 1; seg >= 0; --seg) {
         const int64_t nA = seg * K, nB = min(nA + K, NS);
         // ---- the segment's applied fields and loss weights, in parallel
         __syncthreads();
-        for (int k = i; k <= nB - nA; k += NT) {
+        for (int k = t; k <= nB - nA; k += NT) {
             s_hz[k] = static_cast<float>(L.hz_amp * wave_at(L, nA + k));
             s_w0[k] = static_cast<float>(w[nA + k] / N);
             s_w1[k] = static_cast<float>(w[(NS + 1) + nA + k] / N);
         }
         // ---- forward replay of the segment from its checkpoint
-        float (*A)[NT] = AA[0];
-        float (*B)[NT] = BB[0];
-        V3 m = V3{0, 0, 0};
-        if (on) {
-            const float* c = ckpt + I.ckpt_off + seg * 3 * static_cast<int64_t>(N);
-            m = V3{c[i], c[N + i], c[2 * N + i]};
-            put(A, m);
+        float (*A)[NC] = AA[0];
+        float (*B)[NC] = BB[0];
+        V3 m[KC];
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            m[k] = V3{0, 0, 0};
+            if (on[k]) {
+                const float* c = ckpt + I.ckpt_off + seg * 3 * static_cast<int64_t>(N);
+                m[k] = V3{c[ci[k]], c[N + ci[k]], c[2 * N + ci[k]]};
+                put(A, ci[k], m[k]);
+            }
         }
         if (draws) draw(nA);
         __syncthreads();
         for (int64_t n = nA; n < nB; ++n) {
-            float* t = tp + (n - nA) * 9 * N;
-            V3 q, hth, mp;
+            float* tn = tp + (n - nA) * 9 * N;
+            V3 q[KC], hth[KC], mp[KC];
             // the noise of step n + 1 (its buffer was last read before the
             // previous step's second barrier)
             if (draws && n + 1 < nB) draw(n + 1);
-            if (on) {
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                if (!on[k]) continue;
+                const int i = ci[k];
                 const float hz0 = s_hz[n - nA];
                 V3 xi;
                 if (NP) {
@@ -182,140 +206,157 @@ __global__ __launch_bounds__(kAdjThreads<NT>) void k_adjoint(const InstDev* __re
                     xi = gauss3(philox_cell(I.seed, static_cast<uint32_t>(L.level_tag), kTagNoise,
                                             static_cast<uint32_t>(i), static_cast<uint64_t>(n)));
                 }
-                hth = V3{sigma * xi.x, sigma * xi.y, sigma * xi.z};
-                heun_predict(Lc, m, nb(A, m), u, hz0, hth, mp, q);
-                put(B, mp);
-                t[i] = m.x;
-                t[N + i] = m.y;
-                t[2 * N + i] = m.z;
-                t[3 * N + i] = mp.x;
-                t[4 * N + i] = mp.y;
-                t[5 * N + i] = mp.z;
-                t[6 * N + i] = xi.x;
-                t[7 * N + i] = xi.y;
-                t[8 * N + i] = xi.z;
+                hth[k] = V3{sigma * xi.x, sigma * xi.y, sigma * xi.z};
+                heun_predict(Lc, m[k], nb(A, m[k], k), u[k], hz0, hth[k], mp[k], q[k]);
+                put(B, i, mp[k]);
+                tn[i] = m[k].x;
+                tn[N + i] = m[k].y;
+                tn[2 * N + i] = m[k].z;
+                tn[3 * N + i] = mp[k].x;
+                tn[4 * N + i] = mp[k].y;
+                tn[5 * N + i] = mp[k].z;
+                tn[6 * N + i] = xi.x;
+                tn[7 * N + i] = xi.y;
+                tn[8 * N + i] = xi.z;
             }
             __syncthreads();
-            if (on) {
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                if (!on[k]) continue;
                 const float hz1 = s_hz[n + 1 - nA];
-                m = heun_correct(Lc, mp, nb(B, mp), u, hz1, hth, q);
-                put(A, m);
+                m[k] = heun_correct(Lc, mp[k], nb(B, mp[k], k), u[k], hz1, hth[k], q[k]);
+                put(A, ci[k], m[k]);
             }
             __syncthreads();
         }
         // the tape of the segment's last step in LDS and registers, the step
         // before it in registers: each reverse step puts the tape of the step
         // before it into the other parity and loads the one before that
-        auto load_tape = [&](int64_t n, V3& a, V3& b, V3& c) {
-            const float* t = tp + (n - nA) * 9 * N;
-            a = V3{t[i], t[N + i], t[2 * N + i]};
-            b = V3{t[3 * N + i], t[4 * N + i], t[5 * N + i]};
-            c = V3{t[6 * N + i], t[7 * N + i], t[8 * N + i]};
+        auto load_tape = [&](int64_t n, int i, V3& a, V3& b, V3& c) {
+            const float* tt = tp + (n - nA) * 9 * N;
+            a = V3{tt[i], tt[N + i], tt[2 * N + i]};
+            b = V3{tt[3 * N + i], tt[4 * N + i], tt[5 * N + i]};
+            c = V3{tt[6 * N + i], tt[7 * N + i], tt[8 * N + i]};
         };
-        V3 cm = V3{0, 0, 0}, cp = V3{0, 0, 0}, cx = V3{0, 0, 0};   // step n
-        V3 tm = V3{0, 0, 0}, tp_ = V3{0, 0, 0}, tx = V3{0, 0, 0};  // step n - 1
-        if (on) {
-            load_tape(nB - 1, cm, cp, cx);
-            put(AA[(nB - 1) & 1], cm);
-            put(BB[(nB - 1) & 1], cp);
-            if (nB - 1 > nA) load_tape(nB - 2, tm, tp_, tx);
+        V3 cm[KC], cp[KC], cx[KC];   // step n
+        V3 tm[KC], tq[KC], tx[KC];   // step n - 1
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            cm[k] = cp[k] = cx[k] = tm[k] = tq[k] = tx[k] = V3{0, 0, 0};
+            if (on[k]) {
+                load_tape(nB - 1, ci[k], cm[k], cp[k], cx[k]);
+                put(AA[(nB - 1) & 1], ci[k], cm[k]);
+                put(BB[(nB - 1) & 1], ci[k], cp[k]);
+                if (nB - 1 > nA) load_tape(nB - 2, ci[k], tm[k], tq[k], tx[k]);
+            }
         }
         __syncthreads();
         // ---- reverse walk of the segment
         for (int64_t n = nB - 1; n >= nA; --n) {
-            const V3 mm = cm, mp = cp, xi = cx;
-            float (*A)[NT] = AA[n & 1];
-            float (*B)[NT] = BB[n & 1];
-            V3 ex, exq, H, f, Hp, fp, mn, mpb[2], mb[2], fb[2];
-            float ip = 0.f, iq = 0.f;
-            if (on) {
+            float (*A)[NC] = AA[n & 1];
+            float (*B)[NC] = BB[n & 1];
+            V3 mm[KC], mpk[KC], xik[KC], ex[KC], exq[KC], H[KC], f[KC], mpb[KC][2], mb[KC][2], fb[KC][2];
+            float ip[KC];
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                mm[k] = cm[k];
+                mpk[k] = cp[k];
+                xik[k] = cx[k];
+                ip[k] = 0.f;
+                if (!on[k]) continue;
+                const V3 mpc = mpk[k];
                 const float hz0 = s_hz[n - nA];
                 const float hz1 = s_hz[n + 1 - nA];
-                const V3 hth = V3{sigma * xi.x, sigma * xi.y, sigma * xi.z};
-                ex = nb(A, mm);
-                H = eff_field(c_ex, hk, mm, ex, u, hz0, hth);
-                f = llg_rhs(g1, ag1, mm, H);
-                const V3 pv = V3{fmaf(dt, f.x, mm.x), fmaf(dt, f.y, mm.y), fmaf(dt, f.z, mm.z)};
-                ip = __builtin_amdgcn_rsqf(dot3(pv, pv));
-                exq = nb(B, mp);
-                Hp = eff_field(c_ex, hk, mp, exq, u, hz1, hth);
-                fp = llg_rhs(g1, ag1, mp, Hp);
+                const V3 hth = V3{sigma * xik[k].x, sigma * xik[k].y, sigma * xik[k].z};
+                ex[k] = nb(A, mm[k], k);
+                H[k] = eff_field(c_ex, hk, mm[k], ex[k], u[k], hz0, hth);
+                f[k] = llg_rhs(g1, ag1, mm[k], H[k]);
+                const V3 pv = V3{fmaf(dt, f[k].x, mm[k].x), fmaf(dt, f[k].y, mm[k].y), fmaf(dt, f[k].z, mm[k].z)};
+                ip[k] = __builtin_amdgcn_rsqf(dot3(pv, pv));
+                exq[k] = nb(B, mpc, k);
+                const V3 Hp = eff_field(c_ex, hk, mpc, exq[k], u[k], hz1, hth);
+                const V3 fp = llg_rhs(g1, ag1, mpc, Hp);
                 // q as the forward step forms it: (m + dt/2 f) + dt/2 f'
-                const V3 q0 = V3{fmaf(half_dt, f.x, mm.x), fmaf(half_dt, f.y, mm.y), fmaf(half_dt, f.z, mm.z)};
+                const V3 q0 = V3{fmaf(half_dt, f[k].x, mm[k].x), fmaf(half_dt, f[k].y, mm[k].y),
+                                 fmaf(half_dt, f[k].z, mm[k].z)};
                 const V3 qv = V3{fmaf(half_dt, fp.x, q0.x), fmaf(half_dt, fp.y, q0.y), fmaf(half_dt, fp.z, q0.z)};
-                iq = __builtin_amdgcn_rsqf(dot3(qv, qv));
-                mn = scale3(iq, qv);
-                const V3 mxH = cross3(mp, Hp);
-                const V3 dmp = cross3(mp, mxH);
+                const float iq = __builtin_amdgcn_rsqf(dot3(qv, qv));
+                const V3 mn = scale3(iq, qv);
+                const V3 mxH = cross3(mpc, Hp);
+                const V3 dmp = cross3(mpc, mxH);
 #pragma unroll
                 for (int l = 0; l < 2; ++l) {
-                    const V3 qb = unit_T(mn, iq, lam[l]);
-                    mb[l] = qb;
+                    const V3 qb = unit_T(mn, iq, lam[k][l]);
+                    mb[k][l] = qb;
                     const V3 fpb = scale3(half_dt, qb);
-                    fb[l] = fpb;
-                    const V3 hpb = rhs_dH_T(g1, ag1, mp, fpb);
-                    mpb[l] = rhs_dm_T(g1, ag1, mp, Hp, fpb);
+                    fb[k][l] = fpb;
+                    const V3 hpb = rhs_dH_T(g1, ag1, mpc, fpb);
+                    mpb[k][l] = rhs_dm_T(g1, ag1, mpc, Hp, fpb);
                     g[l][2] += static_cast<double>(dot3(fpb, fp) * inv_g1);
                     g[l][3] += static_cast<double>(-g1 * dot3(fpb, dmp));
-                    HB[l][0][0][i] = hpb.x;
-                    HB[l][0][1][i] = hpb.y;
-                    HB[l][0][2][i] = hpb.z;
+                    HB[l][0][0][ci[k]] = hpb.x;
+                    HB[l][0][1][ci[k]] = hpb.y;
+                    HB[l][0][2][ci[k]] = hpb.z;
                 }
                 if (n > nA) {
-                    put(AA[(n - 1) & 1], tm);
-                    put(BB[(n - 1) & 1], tp_);
-                    cm = tm;
-                    cp = tp_;
-                    cx = tx;
-                    if (n - 1 > nA) load_tape(n - 2, tm, tp_, tx);
+                    put(AA[(n - 1) & 1], ci[k], tm[k]);
+                    put(BB[(n - 1) & 1], ci[k], tq[k]);
+                    cm[k] = tm[k];
+                    cp[k] = tq[k];
+                    cx[k] = tx[k];
+                    if (n - 1 > nA) load_tape(n - 2, ci[k], tm[k], tq[k], tx[k]);
                 }
             }
             __syncthreads();
-            if (on) {
-                const V3 mxH = cross3(mm, H);
-                const V3 dm = cross3(mm, mxH);
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                if (!on[k]) continue;
+                const V3 mxH = cross3(mm[k], H[k]);
+                const V3 dm = cross3(mm[k], mxH);
 #pragma unroll
                 for (int l = 0; l < 2; ++l) {
-                    float (*S)[NT] = HB[l][0];
-                    const V3 hpb = v3(S[0][i], S[1][i], S[2][i]);
-                    const V3 d = nb(S, hpb);
-                    const float uh = dot3(u, hpb);
-                    V3 v = mpb[l];
-                    v.x = fmaf(c_ex, d.x, fmaf(hk * uh, u.x, v.x));
-                    v.y = fmaf(c_ex, d.y, fmaf(hk * uh, u.y, v.y));
-                    v.z = fmaf(c_ex, d.z, fmaf(hk * uh, u.z, v.z));
-                    g[l][0] += static_cast<double>(dot3(hpb, exq));
-                    g[l][1] += static_cast<double>(dot3(mp, u) * uh);
-                    g[l][4] += static_cast<double>(dot3(hpb, xi));
-                    const V3 pb = unit_T(mp, ip, v);
-                    mb[l] = add3(mb[l], pb);
-                    fb[l] = V3{fmaf(dt, pb.x, fb[l].x), fmaf(dt, pb.y, fb[l].y), fmaf(dt, pb.z, fb[l].z)};
-                    const V3 hb = rhs_dH_T(g1, ag1, mm, fb[l]);
-                    mb[l] = add3(mb[l], rhs_dm_T(g1, ag1, mm, H, fb[l]));
-                    g[l][2] += static_cast<double>(dot3(fb[l], f) * inv_g1);
-                    g[l][3] += static_cast<double>(-g1 * dot3(fb[l], dm));
-                    HB[l][1][0][i] = hb.x;
-                    HB[l][1][1][i] = hb.y;
-                    HB[l][1][2][i] = hb.z;
+                    float (*S)[NC] = HB[l][0];
+                    const V3 hpb = v3(S[0][ci[k]], S[1][ci[k]], S[2][ci[k]]);
+                    const V3 d = nb(S, hpb, k);
+                    const float uh = dot3(u[k], hpb);
+                    V3 v = mpb[k][l];
+                    v.x = fmaf(c_ex, d.x, fmaf(hk * uh, u[k].x, v.x));
+                    v.y = fmaf(c_ex, d.y, fmaf(hk * uh, u[k].y, v.y));
+                    v.z = fmaf(c_ex, d.z, fmaf(hk * uh, u[k].z, v.z));
+                    g[l][0] += static_cast<double>(dot3(hpb, exq[k]));
+                    g[l][1] += static_cast<double>(dot3(mpk[k], u[k]) * uh);
+                    g[l][4] += static_cast<double>(dot3(hpb, xik[k]));
+                    const V3 pb = unit_T(mpk[k], ip[k], v);
+                    mb[k][l] = add3(mb[k][l], pb);
+                    fb[k][l] = V3{fmaf(dt, pb.x, fb[k][l].x), fmaf(dt, pb.y, fb[k][l].y), fmaf(dt, pb.z, fb[k][l].z)};
+                    const V3 hb = rhs_dH_T(g1, ag1, mm[k], fb[k][l]);
+                    mb[k][l] = add3(mb[k][l], rhs_dm_T(g1, ag1, mm[k], H[k], fb[k][l]));
+                    g[l][2] += static_cast<double>(dot3(fb[k][l], f[k]) * inv_g1);
+                    g[l][3] += static_cast<double>(-g1 * dot3(fb[k][l], dm));
+                    HB[l][1][0][ci[k]] = hb.x;
+                    HB[l][1][1][ci[k]] = hb.y;
+                    HB[l][1][2][ci[k]] = hb.z;
                 }
             }
             __syncthreads();
-            if (on) {
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                if (!on[k]) continue;
 #pragma unroll
                 for (int l = 0; l < 2; ++l) {
-                    float (*S)[NT] = HB[l][1];
-                    const V3 hb = v3(S[0][i], S[1][i], S[2][i]);
-                    const V3 d = nb(S, hb);
-                    const float uh = dot3(u, hb);
-                    V3 v = mb[l];
-                    v.x = fmaf(c_ex, d.x, fmaf(hk * uh, u.x, v.x));
-                    v.y = fmaf(c_ex, d.y, fmaf(hk * uh, u.y, v.y));
-                    v.z = fmaf(c_ex, d.z, fmaf(hk * uh, u.z, v.z));
-                    g[l][0] += static_cast<double>(dot3(hb, ex));
-                    g[l][1] += static_cast<double>(dot3(mm, u) * uh);
-                    g[l][4] += static_cast<double>(dot3(hb, xi));
+                    float (*S)[NC] = HB[l][1];
+                    const V3 hb = v3(S[0][ci[k]], S[1][ci[k]], S[2][ci[k]]);
+                    const V3 d = nb(S, hb, k);
+                    const float uh = dot3(u[k], hb);
+                    V3 v = mb[k][l];
+                    v.x = fmaf(c_ex, d.x, fmaf(hk * uh, u[k].x, v.x));
+                    v.y = fmaf(c_ex, d.y, fmaf(hk * uh, u[k].y, v.y));
+                    v.z = fmaf(c_ex, d.z, fmaf(hk * uh, u[k].z, v.z));
+                    g[l][0] += static_cast<double>(dot3(hb, ex[k]));
+                    g[l][1] += static_cast<double>(dot3(mm[k], u[k]) * uh);
+                    g[l][4] += static_cast<double>(dot3(hb, xik[k]));
                     v.z += (l == 0 ? s_w0 : s_w1)[n - nA];
-                    lam[l] = v;
+                    lam[k][l] = v;
                 }
             }
             // no barrier: the next step reads m_n, m' of the other parity
@@ -325,19 +366,19 @@ __global__ __launch_bounds__(kAdjThreads<NT>) void k_adjoint(const InstDev* __re
         }
     }
     // ---- FP64 block reduction in fixed order (cell threads)
-    const int lane = i & 63, wv = i >> 6;
+    const int lane = t & 63, wv = t >> 6;
     if (!noise_thread) {
         for (int l = 0; l < 2; ++l)
             for (int k = 0; k < 5; ++k) {
-                const double s = wave_sum_d(g[l][k]);
-                if (lane == 0) red[wv][l * 5 + k] = s;
+                const double sum = wave_sum_d(g[l][k]);
+                if (lane == 0) red[wv][l * 5 + k] = sum;
             }
     }
     __syncthreads();
-    if (!noise_thread && i < 10) {
-        double s = 0.0;
-        for (int k = 0; k < NT / 64; ++k) s += red[k][i];
-        grads[static_cast<int64_t>(inst) * 10 + i] = s;
+    if (!noise_thread && t < 10) {
+        double sum = 0.0;
+        for (int k = 0; k < NT / 64; ++k) sum += red[k][t];
+        grads[static_cast<int64_t>(inst) * 10 + t] = sum;
     }
 }
 

@@ -2317,7 +2317,7 @@ int sllg_grad(sllg_ctx* C, int32_t level, double g_area[4], double g_hc[4])
         return fail(SLLG_E_STATE, "sllg_grad needs checkpoints: pass ckpt_every > 0 to sllg_init");
     if (h.in.record_every != 1) return fail(SLLG_E_STATE, "sllg_grad needs record_every == 1");
     if (h.step != h.n_steps) return fail(SLLG_E_STATE, "run the whole sweep before sllg_grad");
-    if (h.ncell > 1024) return fail(SLLG_E_INVAL, "the adjoint holds at most 1024 cells per realization");
+    if (h.ncell > 1536) return fail(SLLG_E_INVAL, "the adjoint holds at most 1536 cells per realization");
     if (C->mat.demag) return fail(SLLG_E_STATE, "the adjoint has no magnetostatic term");
     int rc = check_status(C);
     if (rc) return rc;
@@ -2353,29 +2353,34 @@ int sllg_grad(sllg_ctx* C, int32_t level, double g_area[4], double g_hc[4])
     }
     for (double& x : w) x /= (double)R;
     HIP_OK(hipMemcpyAsync(C->d_weights, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice, C->stream));
+    // threads and cells per thread: one cell per thread up to 1024 cells,
+    // two per thread (768 threads) up to 1536
     const int nt = h.ncell <= 64 ? 64 : h.ncell <= 128 ? 128 : h.ncell <= 192 ? 192 : h.ncell <= 256 ? 256
-                 : h.ncell <= 512 ? 512 : 1024;
+                 : h.ncell <= 512 ? 512 : h.ncell <= 1024 ? 1024 : 768;
+    const int kc = h.ncell <= 1024 ? 1 : 2;
     // dynamic LDS: the segment's loss weights and applied field (three FP32
     // per step); static LDS: m_n and m' of two parities, four H-bar planes,
-    // replay noise of two parities, sums
+    // replay noise of two parities (noise threads), sums
     const size_t seg_lds = 12 * (size_t)(C->ckpt_every + 1);
-    const size_t static_lds = (size_t)nt * (2 * 2 * 3 * 4 + 2 * 2 * 3 * 4 + 2 * 3 * 4) + (size_t)(nt / 64) * 10 * 8;
+    const size_t static_lds = (size_t)nt * kc * (2 * 2 * 3 * 4 + 2 * 2 * 3 * 4) +
+                              (kc == 1 && nt <= 256 ? (size_t)nt * 2 * 3 * 4 : 24) + (size_t)(nt / 64) * 10 * 8;
     if (seg_lds + static_lds > (size_t)C->max_lds)
         return fail(SLLG_E_INVAL, "ckpt_every %d too large for the adjoint's LDS (at most %d)", C->ckpt_every,
                     (int)((C->max_lds - static_lds) / 12) - 1);
-#define SLLG_ADJ(NT)                                                                                          \
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adjoint<NT>),                                  \
+#define SLLG_ADJ(NT, KC)                                                                                      \
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adjoint<NT, KC>),                              \
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)seg_lds);                      \
-    hipLaunchKernelGGL(k_adjoint<NT>, dim3((unsigned)R), dim3(kAdjThreads<NT>), seg_lds, C->stream,          \
+    hipLaunchKernelGGL((k_adjoint<NT, KC>), dim3((unsigned)R), dim3(kAdjThreads<NT, KC>), seg_lds, C->stream, \
                        C->d_insts, h.inst0,                                                                   \
                        C->d_levels, C->d_axes, C->d_ckpt, C->ckpt_every, C->d_tape, C->d_weights, C->d_grads)
-    switch (nt) {
-    case 64: SLLG_ADJ(64); break;
-    case 128: SLLG_ADJ(128); break;
-    case 192: SLLG_ADJ(192); break;
-    case 256: SLLG_ADJ(256); break;
-    case 512: SLLG_ADJ(512); break;
-    default: SLLG_ADJ(1024); break;
+    switch (nt * 10 + kc) {
+    case 641: SLLG_ADJ(64, 1); break;
+    case 1281: SLLG_ADJ(128, 1); break;
+    case 1921: SLLG_ADJ(192, 1); break;
+    case 2561: SLLG_ADJ(256, 1); break;
+    case 5121: SLLG_ADJ(512, 1); break;
+    case 10241: SLLG_ADJ(1024, 1); break;
+    default: SLLG_ADJ(768, 2); break;
     }
 #undef SLLG_ADJ
     HIP_OK(hipGetLastError());

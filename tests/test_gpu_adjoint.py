@@ -70,10 +70,12 @@ def test_short_sweep_area_gradient(P, orc):
     assert ok, (ga, ra, r)
 
 
-@pytest.mark.parametrize("dims", [(2, 4, 7), (4, 8, 12)])
+@pytest.mark.parametrize("dims", [(2, 4, 7), (4, 8, 12), (8, 8, 16), (4, 12, 28), (5, 7, 31)])
 def test_area_gradient_other_workgroup_sizes(P, orc, dims):
-    # 56 cells (64 threads + noise threads) and 384 cells (512 threads, the
-    # replay draws its noise inline)
+    # 56 cells (64 threads + noise threads), 384 cells (512 threads, the
+    # replay draws its noise inline), 1024 cells (one per thread), the rod at
+    # b = 2 (1344 cells) and a ragged 1085 cells (768 threads, two cells per
+    # thread)
     wl = W.workload("rod_b4_adjoint64")
     wl["material"]["sweep_Oe_per_ns"] *= 40        # 1000 steps
     wl["levels"][0].update(nx=dims[0], ny=dims[1], nz=dims[2], n_real=2)
@@ -195,6 +197,27 @@ def test_switching_gradients_against_oracle_finite_differences(P, orc):
     print("coercive field:", gh, fH, rH)
     assert np.all(rS <= 1e-3), rS
     assert np.all(rH <= 1e-3), rH
+
+
+def test_grad_size_limits(P):
+    # more than 1536 cells, or a segment whose tables do not fit LDS beside
+    # the 1344-cell level's state: refused before any kernel runs
+    wl = W.workload("rod_b4_adjoint64")
+    wl["material"]["sweep_Oe_per_ns"] *= 200       # 200 steps
+    for dims, ckpt in (((8, 8, 25), 64), ((4, 12, 28), 1283)):
+        wl["levels"][0].update(nx=dims[0], ny=dims[1], nz=dims[2], n_real=1)
+        sim = P.Sim(wl["material"], wl["levels"], ckpt_every=ckpt)
+        sim.run_sweep()
+        with pytest.raises(P.SllgError) as e:
+            sim.grad(0)
+        assert e.value.code == -1, dims
+        sim.close()
+    wl["levels"][0].update(nx=4, ny=12, nz=28)
+    sim = P.Sim(wl["material"], wl["levels"], ckpt_every=1282)
+    sim.run_sweep()
+    ga, _ = sim.grad(0)
+    assert np.all(np.isfinite(ga))
+    sim.close()
 
 
 def test_grad_requires_checkpoints_and_full_sweep(P):
