@@ -148,7 +148,7 @@ def dominant_kernel(sim, n_levels):
 def roofline(sim, wl, name, k_ms, k_n, k_cells):
     """Roofline object of the dominant kernel from its mean launch time."""
     levels = wl["levels"]
-    dom, fam, _ = dominant_kernel(sim, len(levels))
+    dom, fam, kernels = dominant_kernel(sim, len(levels))
     if not (k_n > 0 and k_ms > 0):
         return None
     spl = 1
@@ -157,6 +157,10 @@ def roofline(sim, wl, name, k_ms, k_n, k_cells):
         spl = int(mt.group(1))
     launch_ms = k_ms * spl            # a slab launch covers spl steps
     per_launch = k_cells * spl        # cell-updates per launch
+    # steps one launch advances its levels (resident, lanes and demag
+    # launches run many steps; a streamed launch one)
+    dom_cells = sum(l["nx"] * l["ny"] * l["nz"] * l["n_real"] for l, k in zip(levels, kernels) if k == dom)
+    steps_per_launch = per_launch / dom_cells if dom_cells else None
     has_axes = any(l.get("cone_deg", 0) > 0 for l in levels)
     bpc = BYTES_PER_CELL_UPDATE + (BYTES_AXES if has_axes else 0)
     fpc = FLOPS_PER_CELL_UPDATE
@@ -179,7 +183,8 @@ def roofline(sim, wl, name, k_ms, k_n, k_cells):
         rl = {"bound": "alu", "achieved": round(tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
               "frac": round(tflops / PEAK_FP32_TFLOPS, 4), "traffic": traffic}
     rl.update({
-        "kernel": dom, "mean_launch_ms": launch_ms, "steps_per_launch": spl,
+        "kernel": dom, "mean_launch_ms": launch_ms,
+        "steps_per_launch": round(steps_per_launch, 2) if steps_per_launch else None,
         "launches_timed": k_n // spl if spl > 1 else k_n, "cell_updates_per_launch": per_launch,
         "bytes_per_cell_update": bpc, "algorithmic_bytes_per_launch": per_launch * bpc,
         "flops_per_cell_update": fpc,

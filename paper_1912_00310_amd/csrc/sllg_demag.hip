@@ -1,16 +1,23 @@
 // Heun step with the magnetostatic (demagnetising) field, for levels of up to
-// 1024 cells: one workgroup per realization, one cell per thread, the state in
+// 1024 cells: one workgroup per realization, the state and the tensor table in
 // LDS for a launch of many steps.
 //
 // Beyond the paper, which leaves magnetostatics out (shape anisotropy is
 // folded into K; material paragraph and closing discussion).  The field on
 // cell i is Hd_i = sum_j T(r_i - r_j) m_j with T = -Ms N the demagnetising
-// tensor of two uniformly magnetised cubes, tabulated by the host for every
-// offset between two cells of the grid (8 floats per offset: xx yy zz xy |
-// xz yz 0 0).  The sum is direct: every thread walks all cells, the m_j reads
-// are LDS broadcasts (all lanes read the same cell) and the tensor reads come
-// from the cached table.  Hd is added to the thermal field (both enter the
-// effective field as plain additive terms), so the per-cell Heun functions
+// tensor of two uniformly magnetised cubes.  N is even in every component of
+// the offset on its diagonal, and N_xy is odd in dx and dy (even in dz), N_xz
+// odd in dx and dz, N_yz odd in dy and dz; so the host tabulates only offsets
+// with dx, dy, dz >= 0 (one per cell of the grid, six planes xx yy zz xy xz
+// yz of ncell floats) and the kernel restores the signs.
+//
+// The sum is direct, split over S groups of threads: thread s*N + i sums the
+// cells of chunk s for cell i (the m_j reads are LDS broadcasts, the table
+// reads run over consecutive cells), the partial sums meet in LDS and the
+// owner thread i (s = 0) adds them in chunk order and takes the Heun stage.
+// S depends only on the cell count, so the summation order, and hence every
+// state, is fixed by the level.  Hd is added to the thermal field (both enter
+// the effective field as plain additive terms), so the per-cell Heun functions
 // are those of every other kernel; the field is recomputed for m' in the
 // corrector.
 #include <hip/hip_runtime.h>
@@ -20,51 +27,86 @@
 
 namespace sllg {
 
-template <int NT>
-__device__ __forceinline__ V3 demag_sum(const float* __restrict__ S, const float4* __restrict__ T, int x, int y,
-                                        int z, int nx, int ny, int nz, int N)
+constexpr int kDemagMaxThreads = 1024;
+constexpr int kDemagMaxCells = 1024;
+
+// Chunks of the direct sum for a level of n cells: about 1024/n, at most 16,
+// every chunk non-empty.  Threads of the workgroup: chunks x n, rounded up to
+// whole waves.
+__host__ __device__ constexpr int demag_chunk_len(int n)
 {
-    const int wx = 2 * nx - 1, wy = 2 * ny - 1;
+    const int s0 = n >= kDemagMaxThreads ? 1 : (kDemagMaxThreads / n > 16 ? 16 : kDemagMaxThreads / n);
+    return (n + s0 - 1) / s0;
+}
+__host__ __device__ constexpr int demag_chunks(int n) { return (n + demag_chunk_len(n) - 1) / demag_chunk_len(n); }
+__host__ __device__ constexpr int demag_block(int n) { return (demag_chunks(n) * n + 63) / 64 * 64; }
+
+__device__ __forceinline__ float sgnf(int d) { return static_cast<float>((d > 0) - (d < 0)); }
+
+// Partial field on cell (x, y, z) from cells j0 .. j1-1 of the state planes S.
+__device__ __forceinline__ V3 demag_partial(const float* __restrict__ S, const float* __restrict__ Tt, int x, int y,
+                                            int z, int nx, int ny, int N, int j0, int j1)
+{
     V3 h = V3{0.0f, 0.0f, 0.0f};
-    int j = 0;
-    for (int zj = 0; zj < nz; ++zj)
-        for (int yj = 0; yj < ny; ++yj) {
-            // offset index of (x - xj, y - yj, z - zj) for xj = 0; it falls by
-            // one per step in xj
-            int o = ((z - zj + nz - 1) * wy + (y - yj + ny - 1)) * wx + x + nx - 1;
-            for (int xj = 0; xj < nx; ++xj, ++j, --o) {
-                const float4 a = T[2 * o], b = T[2 * o + 1];   // xx yy zz xy | xz yz
-                const float mx = S[j], my = S[N + j], mz = S[2 * N + j];
-                h.x = fmaf(a.x, mx, fmaf(a.w, my, fmaf(b.x, mz, h.x)));
-                h.y = fmaf(a.w, mx, fmaf(a.y, my, fmaf(b.y, mz, h.y)));
-                h.z = fmaf(b.x, mx, fmaf(b.y, my, fmaf(a.z, mz, h.z)));
+    int xj = j0 % nx, yj = (j0 / nx) % ny, zj = j0 / (nx * ny);
+    int dy = y - yj, dz = z - zj;
+    int rowo = nx * (abs(dy) + ny * abs(dz));
+    float syz = sgnf(dy) * sgnf(dz), sy = sgnf(dy), sz = sgnf(dz);
+    for (int j = j0; j < j1; ++j) {
+        const int dx = x - xj;
+        const int o = rowo + abs(dx);
+        const float sx = sgnf(dx);
+        const float txx = Tt[o], tyy = Tt[N + o], tzz = Tt[2 * N + o];
+        const float txy = sx * sy * Tt[3 * N + o], txz = sx * sz * Tt[4 * N + o], tyz = syz * Tt[5 * N + o];
+        const float mx = S[j], my = S[N + j], mz = S[2 * N + j];
+        h.x = fmaf(txx, mx, fmaf(txy, my, fmaf(txz, mz, h.x)));
+        h.y = fmaf(txy, mx, fmaf(tyy, my, fmaf(tyz, mz, h.y)));
+        h.z = fmaf(txz, mx, fmaf(tyz, my, fmaf(tzz, mz, h.z)));
+        if (++xj == nx) {
+            xj = 0;
+            if (++yj == ny) {
+                yj = 0;
+                ++zj;
+                dz = z - zj;
+                sz = sgnf(dz);
             }
+            dy = y - yj;
+            sy = sgnf(dy);
+            syz = sy * sz;
+            rowo = nx * (abs(dy) + ny * abs(dz));
         }
+    }
     return h;
 }
 
-template <int NT>
-__global__ __launch_bounds__(NT) void k_demag(const InstDev* __restrict__ insts, int inst0,
-                                              const LevelDev* __restrict__ levels, float* __restrict__ buf0,
-                                              float* __restrict__ buf1, const float* __restrict__ axes,
-                                              const float* __restrict__ demag, double* __restrict__ records,
-                                              AccDev* __restrict__ accs, float* __restrict__ ckpt, int ckpt_every,
-                                              int64_t n0, int64_t nsteps, int* __restrict__ status)
+__global__ __launch_bounds__(kDemagMaxThreads) void k_demag(const InstDev* __restrict__ insts, int inst0,
+                                                           const LevelDev* __restrict__ levels,
+                                                           float* __restrict__ buf0, float* __restrict__ buf1,
+                                                           const float* __restrict__ axes,
+                                                           const float* __restrict__ demag,
+                                                           double* __restrict__ records, AccDev* __restrict__ accs,
+                                                           float* __restrict__ ckpt, int ckpt_every, int64_t n0,
+                                                           int64_t nsteps, int* __restrict__ status)
 {
-    __shared__ float A[3 * NT];    // m_n, planes x | y | z of N cells
-    __shared__ float B[3 * NT];    // m'
-    __shared__ double red[NT / 64];
+    __shared__ float Tt[6 * kDemagMaxCells];   // tensor planes xx yy zz xy xz yz
+    __shared__ float A[3 * kDemagMaxCells];    // m_n, planes x | y | z of N cells
+    __shared__ float B[3 * kDemagMaxCells];    // m'
+    __shared__ float P[3 * kDemagMaxThreads];  // partial sums of chunks 1 .. S-1
+    __shared__ double red[kDemagMaxThreads / 64];
+    __shared__ AccDev acc;                     // the loop accumulators (thread 0)
     const int inst = inst0 + static_cast<int>(blockIdx.x);
     const InstDev I = insts[inst];
     const LevelDev& L = levels[I.level];
     const int N = L.ncell, nx = L.nx, ny = L.ny, nz = L.nz;
-    const int i = static_cast<int>(threadIdx.x);
-    const bool on = i < N;
-    const int x = on ? i % nx : 0, y = on ? (i / nx) % ny : 0, z = on ? i / (nx * ny) : 0;
-    const int ixm = x > 0 ? i - 1 : i, ixp = x < nx - 1 ? i + 1 : i;
-    const int iym = y > 0 ? i - nx : i, iyp = y < ny - 1 ? i + nx : i;
-    const int izm = z > 0 ? i - nx * ny : i, izp = z < nz - 1 ? i + nx * ny : i;
-    const float4* T = reinterpret_cast<const float4*>(demag + L.demag_off);
+    const int tid = static_cast<int>(threadIdx.x), nthr = static_cast<int>(blockDim.x);
+    const int clen = demag_chunk_len(N), S = demag_chunks(N);
+    const int s = tid / N, i = tid - s * N;
+    const bool sums = s < S;                 // computes a partial sum
+    const bool on = tid < N;                 // owns cell i
+    const int j0 = sums ? s * clen : 0, j1 = sums ? min(N, j0 + clen) : 0;
+    const int x = sums ? i % nx : 0, y = sums ? (i / nx) % ny : 0, z = sums ? i / (nx * ny) : 0;
+    const float* T = demag + L.demag_off;
+    for (int k = tid; k < 6 * N; k += nthr) Tt[k] = T[k];
     const float* mi = ((n0 & 1) ? buf1 : buf0) + I.state_off;
     V3 m = V3{0.0f, 0.0f, 0.0f};
     V3 u = V3{L.ux, L.uy, L.uz};
@@ -75,24 +117,49 @@ __global__ __launch_bounds__(NT) void k_demag(const InstDev* __restrict__ insts,
         A[N + i] = m.y;
         A[2 * N + i] = m.z;
     }
-    AccDev a{};
-    if (i == 0) a = accs[inst];
+    if (tid == 0) acc = accs[inst];
     double* rec = records + I.rec_off;
-    auto nb = [&](const float* S, V3 c) {
-        return nb_sum(c, V3{S[ixm], S[N + ixm], S[2 * N + ixm]}, V3{S[ixp], S[N + ixp], S[2 * N + ixp]},
-                      V3{S[iym], S[N + iym], S[2 * N + iym]}, V3{S[iyp], S[N + iyp], S[2 * N + iyp]},
-                      V3{S[izm], S[N + izm], S[2 * N + izm]}, V3{S[izp], S[N + izp], S[2 * N + izp]});
+    // the exchange neighbours are recomputed from (x, y, z) at each use
+    // (fewer live registers across the Heun stages)
+    auto nb = [&](const float* St, V3 c) {
+        const int ixm = x > 0 ? i - 1 : i, ixp = x < nx - 1 ? i + 1 : i;
+        const int iym = y > 0 ? i - nx : i, iyp = y < ny - 1 ? i + nx : i;
+        const int izm = z > 0 ? i - nx * ny : i, izp = z < nz - 1 ? i + nx * ny : i;
+        return nb_sum(c, V3{St[ixm], St[N + ixm], St[2 * N + ixm]}, V3{St[ixp], St[N + ixp], St[2 * N + ixp]},
+                      V3{St[iym], St[N + iym], St[2 * N + iym]}, V3{St[iyp], St[N + iyp], St[2 * N + iyp]},
+                      V3{St[izm], St[N + izm], St[2 * N + izm]}, V3{St[izp], St[N + izp], St[2 * N + izp]});
     };
-    double w = wave_at(L, n0);
-    float hz0 = static_cast<float>(L.hz_amp * w);
-    double H0 = L.hz_oe * w;
+    // partial sum of the thread's chunk over the state St; chunks 1 .. S-1
+    // park theirs in P, the owner keeps chunk 0's in registers
+    auto partial = [&](const float* St) {
+        V3 h = V3{0.0f, 0.0f, 0.0f};
+        if (sums) h = demag_partial(St, Tt, x, y, z, nx, ny, N, j0, j1);
+        if (sums && s > 0) {
+            const int p = (s - 1) * N + i;
+            P[p] = h.x;
+            P[(S - 1) * N + p] = h.y;
+            P[2 * (S - 1) * N + p] = h.z;
+        }
+        return h;
+    };
+    // the owner's total: chunk 0, then chunks 1 .. S-1 in order
+    auto total = [&](V3 h) {
+        for (int c = 1; c < S; ++c) {
+            const int p = (c - 1) * N + i;
+            h.x += P[p];
+            h.y += P[(S - 1) * N + p];
+            h.z += P[2 * (S - 1) * N + p];
+        }
+        return h;
+    };
+    float hz0 = static_cast<float>(L.hz_amp * wave_at(L, n0));
     __syncthreads();
     for (int64_t st = 0; st < nsteps; ++st) {
         const int64_t n = n0 + st;
-        w = wave_at(L, n + 1);
-        const float hz1 = static_cast<float>(L.hz_amp * w);
-        const double H1 = L.hz_oe * w;
+        const float hz1 = static_cast<float>(L.hz_amp * wave_at(L, n + 1));
         V3 mp = V3{0.0f, 0.0f, 0.0f}, q = V3{0.0f, 0.0f, 0.0f}, hth = V3{0.0f, 0.0f, 0.0f};
+        V3 hd = partial(A);
+        __syncthreads();
         if (on) {
             if (ckpt != nullptr && ckpt_every > 0 && (n % ckpt_every) == 0) {
                 float* cp = ckpt + I.ckpt_off + (n / ckpt_every) * 3 * static_cast<int64_t>(N);
@@ -101,16 +168,18 @@ __global__ __launch_bounds__(NT) void k_demag(const InstDev* __restrict__ insts,
                 cp[2 * N + i] = m.z;
             }
             hth = thermal_field(L, I.seed, static_cast<uint32_t>(i), n);
-            const V3 hd = demag_sum<NT>(A, T, x, y, z, nx, ny, nz, N);
+            hd = total(hd);
             heun_predict(L, m, nb(A, m), u, hz0, V3{hth.x + hd.x, hth.y + hd.y, hth.z + hd.z}, mp, q);
             B[i] = mp.x;
             B[N + i] = mp.y;
             B[2 * N + i] = mp.z;
         }
         __syncthreads();
+        hd = partial(B);
+        __syncthreads();
         float mz = 0.0f;
         if (on) {
-            const V3 hd = demag_sum<NT>(B, T, x, y, z, nx, ny, nz, N);
+            hd = total(hd);
             m = heun_correct(L, mp, nb(B, mp), u, hz1, V3{hth.x + hd.x, hth.y + hd.y, hth.z + hd.z}, q);
             // nobody reads m_n after the first barrier of the step
             A[i] = m.x;
@@ -118,11 +187,17 @@ __global__ __launch_bounds__(NT) void k_demag(const InstDev* __restrict__ insts,
             A[2 * N + i] = m.z;
             mz = m.z;
         }
-        // block sum (its barrier also ends the step: A holds m_{n+1})
-        const double tot = block_sum<NT>(mz, red);
-        if (i == 0) loop_accumulate_h(a, L, H0, H1, tot / static_cast<double>(N), rec);
+        // block sum over whole waves (its barrier also ends the step: A
+        // holds m_{n+1}; the next partial sums overwrite P only after it)
+        const float ws = wave_sum(mz);
+        if ((tid & 63) == 0) red[tid >> 6] = static_cast<double>(ws);
+        __syncthreads();
+        if (tid == 0) {
+            double tot = 0.0;
+            for (int k = 0; k < nthr / 64; ++k) tot += red[k];
+            loop_accumulate(acc, L, n, tot / static_cast<double>(N), rec);
+        }
         hz0 = hz1;
-        H0 = H1;
         __syncthreads();
     }
     float* mo = (((n0 + nsteps) & 1) ? buf1 : buf0) + I.state_off;
@@ -131,9 +206,9 @@ __global__ __launch_bounds__(NT) void k_demag(const InstDev* __restrict__ insts,
         mo[N + i] = m.y;
         mo[2 * N + i] = m.z;
     }
-    if (i == 0) {
-        accs[inst] = a;
-        if (!isfinite(a.m_prev)) atomicOr(status, 1);
+    if (tid == 0) {
+        accs[inst] = acc;
+        if (!isfinite(acc.m_prev)) atomicOr(status, 1);
     }
 }
 

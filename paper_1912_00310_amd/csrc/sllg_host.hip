@@ -145,10 +145,11 @@ struct Layout {
         max_tiles, max_groups, max_chunks, max_w, ninst_total, max_slabs, xch_words, demag_floats;
 };
 
-// Floats of the demagnetising-tensor table of a grid: 8 per cell offset.
+// Floats of the demagnetising-tensor table of a grid: six per cell (offsets
+// with non-negative components only).
 int64_t demag_table_floats(const sllg_level& L)
 {
-    return 8LL * (2 * L.nx - 1) * (2 * L.ny - 1) * (2 * L.nz - 1);
+    return 6LL * L.nx * L.ny * L.nz;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -321,7 +322,7 @@ int validate(const sllg_material* m, const sllg_level* L, int n)
         if (l.dt_s < 0 || !std::isfinite(l.dt_s)) return fail(SLLG_E_INVAL, "level %d: dt must be >= 0", i);
         if (!(l.cone_deg >= 0) || l.cone_deg >= 90) return fail(SLLG_E_INVAL, "level %d: cone in [0, 90)", i);
         if (l.record_every < 1) return fail(SLLG_E_INVAL, "level %d: record_every must be >= 1", i);
-        if (m->demag && (int64_t)l.nx * l.ny * l.nz > 1024)
+        if (m->demag && (int64_t)l.nx * l.ny * l.nz > kDemagMaxCells)
             return fail(SLLG_E_INVAL, "level %d: magnetostatics holds at most 1024 cells per realization", i);
     }
     return SLLG_OK;
@@ -384,23 +385,26 @@ ldbl second_differences(F fn, ldbl X, ldbl Y, ldbl Z)
     return -(dy(X + 1) - 2 * dy(X) + dy(X - 1)) / (4 * (ldbl)kPi);
 }
 
-// -Ms N for every offset of an nx x ny x nz grid, 8 floats per offset
-// (xx yy zz xy | xz yz 0 0), offset index ((dz + nz-1)(2ny-1) + dy + ny-1)(2nx-1) + dx + nx-1.
+// -Ms N for the offsets (dx, dy, dz) >= 0 of an nx x ny x nz grid, six
+// planes of ncell floats (xx yy zz xy xz yz), offset index dx + nx (dy + ny dz).
+// The kernel takes the other offsets from the parities of N: the diagonal is
+// even in each component, N_xy odd in dx and dy, N_xz in dx and dz, N_yz in
+// dy and dz.
 void demag_table(const sllg_level& L, double Ms, std::vector<float>& out)
 {
-    const int wx = 2 * L.nx - 1, wy = 2 * L.ny - 1, wz = 2 * L.nz - 1;
-    out.assign((size_t)8 * wx * wy * wz, 0.0f);
-    for (int k = 0; k < wz; ++k)
-        for (int j = 0; j < wy; ++j)
-            for (int i = 0; i < wx; ++i) {
-                const ldbl X = i - L.nx + 1, Y = j - L.ny + 1, Z = k - L.nz + 1;
-                float* o = out.data() + 8 * (((size_t)k * wy + j) * wx + i);
-                o[0] = (float)(-Ms * second_differences(nwl_f, X, Y, Z));
-                o[1] = (float)(-Ms * second_differences(nwl_f, Y, X, Z));
-                o[2] = (float)(-Ms * second_differences(nwl_f, Z, Y, X));
-                o[3] = (float)(-Ms * second_differences(nwl_g, X, Y, Z));
-                o[4] = (float)(-Ms * second_differences(nwl_g, X, Z, Y));
-                o[5] = (float)(-Ms * second_differences(nwl_g, Y, Z, X));
+    const size_t n = (size_t)L.nx * L.ny * L.nz;
+    out.assign(6 * n, 0.0f);
+    for (int k = 0; k < L.nz; ++k)
+        for (int j = 0; j < L.ny; ++j)
+            for (int i = 0; i < L.nx; ++i) {
+                const ldbl X = i, Y = j, Z = k;
+                const size_t o = ((size_t)k * L.ny + j) * L.nx + i;
+                out[o] = (float)(-Ms * second_differences(nwl_f, X, Y, Z));
+                out[n + o] = (float)(-Ms * second_differences(nwl_f, Y, X, Z));
+                out[2 * n + o] = (float)(-Ms * second_differences(nwl_f, Z, Y, X));
+                out[3 * n + o] = (float)(-Ms * second_differences(nwl_g, X, Y, Z));
+                out[4 * n + o] = (float)(-Ms * second_differences(nwl_g, X, Z, Y));
+                out[5 * n + o] = (float)(-Ms * second_differences(nwl_g, Y, Z, X));
             }
 }
 
@@ -903,31 +907,15 @@ hipError_t dispatch_lanes(sllg_ctx* C, int l0, int l1, int64_t n0, int64_t ns)
     return hipGetLastError();
 }
 
-// Levels with magnetostatics: one workgroup per realization, ns steps.
-template <int NT>
-hipError_t launch_demag_t(sllg_ctx* C, int level, int64_t n0, int64_t ns)
-{
-    const LevelHost& h = C->lv[level];
-    hipLaunchKernelGGL(k_demag<NT>, dim3((unsigned)h.ninst), dim3(NT), 0, C->stream, C->d_insts, h.inst0,
-                       C->d_levels, C->d_buf0, C->d_buf1, C->d_axes, C->d_demag, C->d_records, C->d_accs,
-                       C->d_ckpt, C->ckpt_every, n0, ns, C->d_status);
-    return hipGetLastError();
-}
-
-int demag_threads(const LevelHost& h)
-{
-    return h.ncell <= 64 ? 64 : h.ncell <= 128 ? 128 : h.ncell <= 256 ? 256 : h.ncell <= 512 ? 512 : 1024;
-}
-
+// Levels with magnetostatics: one workgroup per realization (chunks x cells
+// threads), ns steps.
 hipError_t dispatch_demag(sllg_ctx* C, int level, int64_t n0, int64_t ns)
 {
-    switch (demag_threads(C->lv[level])) {
-    case 64: return launch_demag_t<64>(C, level, n0, ns);
-    case 128: return launch_demag_t<128>(C, level, n0, ns);
-    case 256: return launch_demag_t<256>(C, level, n0, ns);
-    case 512: return launch_demag_t<512>(C, level, n0, ns);
-    default: return launch_demag_t<1024>(C, level, n0, ns);
-    }
+    const LevelHost& h = C->lv[level];
+    hipLaunchKernelGGL(k_demag, dim3((unsigned)h.ninst), dim3((unsigned)demag_block((int)h.ncell)), 0, C->stream,
+                       C->d_insts, h.inst0, C->d_levels, C->d_buf0, C->d_buf1, C->d_axes, C->d_demag, C->d_records,
+                       C->d_accs, C->d_ckpt, C->ckpt_every, n0, ns, C->d_status);
+    return hipGetLastError();
 }
 
 template <int TX, int TY, int PZ>
@@ -2056,7 +2044,7 @@ int sllg_level_kernel(const sllg_ctx* C, int32_t level, char* name, int32_t cap)
     } else if (h.plan == kPlanLanes) {
         snprintf(buf, sizeof(buf), "k_lanes<%d>", kLanesThreads);
     } else if (h.plan == kPlanDemag) {
-        snprintf(buf, sizeof(buf), "k_demag<%d>", demag_threads(h));
+        snprintf(buf, sizeof(buf), "k_demag %dx%d", demag_chunks((int)h.ncell), (int)h.ncell);
     } else {
         for (const auto& rs : C->res_sets)
             if (std::find(rs.levels.begin(), rs.levels.end(), level) != rs.levels.end())

@@ -60,7 +60,7 @@ def test_demag_rod_first_1000_steps(P, orc):
     print("2x6x14 rod with magnetostatics, worst |dm| over 1000 steps:", worst)
 
 
-@pytest.mark.parametrize("dims", [(1, 1, 1), (3, 2, 5), (7, 7, 7), (8, 8, 16)])
+@pytest.mark.parametrize("dims", [(1, 1, 1), (3, 2, 5), (5, 5, 9), (7, 7, 7), (8, 8, 16)])
 def test_demag_ragged_grids(P, orc, dims):
     wl = demag_rod(dims, n_real=1, sweep_Oe_per_ns=1e5)
     check(P, orc, wl, 200, 100)
