@@ -1712,8 +1712,9 @@ int init_impl(const sllg_material* mat, const sllg_level* levels, int32_t n_leve
         return fail(SLLG_E_WORKSPACE, "workspace must be non-NULL and 256-byte aligned");
     }
     if (ws_bytes < C->lay.total) {
+        const size_t need = C->lay.total;
         delete C;
-        return fail(SLLG_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, C->lay.total);
+        return fail(SLLG_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
     }
     C->ws = (char*)d_workspace;
     C->ws_bytes = ws_bytes;
