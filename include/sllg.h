@@ -293,9 +293,9 @@ int sllg_get_axes(sllg_ctx* ctx, int32_t level, float* host_u);
  * every k-th launch unit (one launch, or one replay of a graph of streamed
  * launches) with HIP events on the context stream; k = 0 switches it off.
  * sllg_kernel_time returns the mean time per kernel launch over the timed
- * units in milliseconds, the number of launches covered, and the
- * cell-updates one launch performs; a launch of the slab plan (3) counts as
- * one launch per step it covers.  It synchronises the stream and restarts
+ * units in milliseconds, the number of launches covered, and the mean
+ * cell-updates per launch (launches of many steps may differ in length);
+ * a launch of the slab plan (3) counts as one launch per step it covers.  It synchronises the stream and restarts
  * the count. */
 int sllg_set_timing(sllg_ctx* ctx, int32_t every);
 int sllg_kernel_time(sllg_ctx* ctx, double* mean_ms, int64_t* launches, int64_t* cells_per_launch);

@@ -5,21 +5,26 @@
 // Beyond the paper, which leaves magnetostatics out (shape anisotropy is
 // folded into K; material paragraph and closing discussion).  The field on
 // cell i is Hd_i = sum_j T(r_i - r_j) m_j with T = -Ms N the demagnetising
-// tensor of two uniformly magnetised cubes.  N is even in every component of
-// the offset on its diagonal, and N_xy is odd in dx and dy (even in dz), N_xz
-// odd in dx and dz, N_yz odd in dy and dz; so the host tabulates only offsets
-// with dx, dy, dz >= 0 (one per cell of the grid, six planes xx yy zz xy xz
-// yz of ncell floats) and the kernel restores the signs.
+// tensor of two uniformly magnetised cubes.  The host tabulates T in one of
+// two forms (six planes xx yy zz xy xz yz):
+//   - wide: every offset of the grid, (2nx-1)(2ny-1)(2nz-1) of them, offset
+//     index ((dz+nz-1)(2ny-1) + dy+ny-1)(2nx-1) + dx+nx-1, used when it fits
+//     the LDS: the index of a pair is base(i) - base(j) with base(j) stored
+//     beside m_j, one subtraction per pair;
+//   - octant: the offsets with dx, dy, dz >= 0 only (one per cell), for the
+//     larger grids: N is even in every component of the offset on its
+//     diagonal, N_xy odd in dx and dy (even in dz), N_xz odd in dx and dz,
+//     N_yz odd in dy and dz, and the kernel restores the signs.
 //
 // The sum is direct, split over S groups of threads: thread s*N + i sums the
-// cells of chunk s for cell i (the m_j reads are LDS broadcasts, the table
-// reads run over consecutive cells), the partial sums meet in LDS and the
-// owner thread i (s = 0) adds them in chunk order and takes the Heun stage.
-// S depends only on the cell count, so the summation order, and hence every
-// state, is fixed by the level.  Hd is added to the thermal field (both enter
-// the effective field as plain additive terms), so the per-cell Heun functions
-// are those of every other kernel; the field is recomputed for m' in the
-// corrector.
+// cells of chunk s for cell i (m_j and base(j) are one LDS broadcast, the
+// table reads run over consecutive cells), the partial sums meet in LDS and
+// the owner thread i (s = 0) adds them in chunk order and takes the Heun
+// stage.  S depends only on the cell count, so the summation order, and hence
+// every state, is fixed by the level.  Hd is added to the thermal field (both
+// enter the effective field as plain additive terms), so the per-cell Heun
+// functions are those of every other kernel; the field is recomputed for m'
+// in the corrector.
 #include <hip/hip_runtime.h>
 
 #include "sllg_device.hpp"
@@ -43,9 +48,29 @@ __host__ __device__ constexpr int demag_block(int n) { return (demag_chunks(n) *
 
 __device__ __forceinline__ float sgnf(int d) { return static_cast<float>((d > 0) - (d < 0)); }
 
-// Partial field on cell (x, y, z) from cells j0 .. j1-1 of the state planes S.
-__device__ __forceinline__ V3 demag_partial(const float* __restrict__ S, const float* __restrict__ Tt, int x, int y,
-                                            int z, int nx, int ny, int N, int j0, int j1)
+// Partial field on cell i from cells j0 .. j1-1 of the state S (xyz of m_j
+// and base(j) in w), wide table.
+__device__ __forceinline__ V3 demag_partial_wide(const float4* __restrict__ S, const float* __restrict__ Tt,
+                                                 int W, int base, int j0, int j1)
+{
+    V3 h = V3{0.0f, 0.0f, 0.0f};
+#pragma unroll 4
+    for (int j = j0; j < j1; ++j) {
+        const float4 mj = S[j];
+        const int o = base - __float_as_int(mj.w);
+        const float txx = Tt[o], tyy = Tt[W + o], tzz = Tt[2 * W + o];
+        const float txy = Tt[3 * W + o], txz = Tt[4 * W + o], tyz = Tt[5 * W + o];
+        h.x = fmaf(txx, mj.x, fmaf(txy, mj.y, fmaf(txz, mj.z, h.x)));
+        h.y = fmaf(txy, mj.x, fmaf(tyy, mj.y, fmaf(tyz, mj.z, h.y)));
+        h.z = fmaf(txz, mj.x, fmaf(tyz, mj.y, fmaf(tzz, mj.z, h.z)));
+    }
+    return h;
+}
+
+// The same with the octant table: the offset's magnitudes index the table
+// and its signs those of the off-diagonal terms.
+__device__ __forceinline__ V3 demag_partial_octant(const float4* __restrict__ S, const float* __restrict__ Tt,
+                                                   int x, int y, int z, int nx, int ny, int N, int j0, int j1)
 {
     V3 h = V3{0.0f, 0.0f, 0.0f};
     int xj = j0 % nx, yj = (j0 / nx) % ny, zj = j0 / (nx * ny);
@@ -58,10 +83,10 @@ __device__ __forceinline__ V3 demag_partial(const float* __restrict__ S, const f
         const float sx = sgnf(dx);
         const float txx = Tt[o], tyy = Tt[N + o], tzz = Tt[2 * N + o];
         const float txy = sx * sy * Tt[3 * N + o], txz = sx * sz * Tt[4 * N + o], tyz = syz * Tt[5 * N + o];
-        const float mx = S[j], my = S[N + j], mz = S[2 * N + j];
-        h.x = fmaf(txx, mx, fmaf(txy, my, fmaf(txz, mz, h.x)));
-        h.y = fmaf(txy, mx, fmaf(tyy, my, fmaf(tyz, mz, h.y)));
-        h.z = fmaf(txz, mx, fmaf(tyz, my, fmaf(tzz, mz, h.z)));
+        const float4 mj = S[j];
+        h.x = fmaf(txx, mj.x, fmaf(txy, mj.y, fmaf(txz, mj.z, h.x)));
+        h.y = fmaf(txy, mj.x, fmaf(tyy, mj.y, fmaf(tyz, mj.z, h.y)));
+        h.z = fmaf(txz, mj.x, fmaf(tyz, mj.y, fmaf(tzz, mj.z, h.z)));
         if (++xj == nx) {
             xj = 0;
             if (++yj == ny) {
@@ -79,21 +104,27 @@ __device__ __forceinline__ V3 demag_partial(const float* __restrict__ S, const f
     return h;
 }
 
+// Static LDS of k_demag; the table is dynamic (6 planes of W floats).
+constexpr size_t kDemagStaticLds =
+    2 * sizeof(float4) * kDemagMaxCells + 3 * sizeof(float) * kDemagMaxThreads + 8 * (kDemagMaxThreads / 64) + 128;
+
+// wide != 0: the table holds every offset (W of them); else the octant
+// table (W = N).
 __global__ __launch_bounds__(kDemagMaxThreads) void k_demag(const InstDev* __restrict__ insts, int inst0,
                                                            const LevelDev* __restrict__ levels,
                                                            float* __restrict__ buf0, float* __restrict__ buf1,
                                                            const float* __restrict__ axes,
-                                                           const float* __restrict__ demag,
+                                                           const float* __restrict__ demag, int wide, int W,
                                                            double* __restrict__ records, AccDev* __restrict__ accs,
                                                            float* __restrict__ ckpt, int ckpt_every, int64_t n0,
                                                            int64_t nsteps, int* __restrict__ status)
 {
-    __shared__ float Tt[6 * kDemagMaxCells];   // tensor planes xx yy zz xy xz yz
-    __shared__ float A[3 * kDemagMaxCells];    // m_n, planes x | y | z of N cells
-    __shared__ float B[3 * kDemagMaxCells];    // m'
-    __shared__ float P[3 * kDemagMaxThreads];  // partial sums of chunks 1 .. S-1
+    extern __shared__ float Tt[];                 // tensor planes xx yy zz xy xz yz of W floats
+    __shared__ float4 A[kDemagMaxCells];          // m_n (xyz) and base(j) (w)
+    __shared__ float4 B[kDemagMaxCells];          // m'
+    __shared__ float P[3 * kDemagMaxThreads];     // partial sums of chunks 1 .. S-1
     __shared__ double red[kDemagMaxThreads / 64];
-    __shared__ AccDev acc;                     // the loop accumulators (thread 0)
+    __shared__ AccDev acc;                        // the loop accumulators (thread 0)
     const int inst = inst0 + static_cast<int>(blockIdx.x);
     const InstDev I = insts[inst];
     const LevelDev& L = levels[I.level];
@@ -105,35 +136,40 @@ __global__ __launch_bounds__(kDemagMaxThreads) void k_demag(const InstDev* __res
     const bool on = tid < N;                 // owns cell i
     const int j0 = sums ? s * clen : 0, j1 = sums ? min(N, j0 + clen) : 0;
     const int x = sums ? i % nx : 0, y = sums ? (i / nx) % ny : 0, z = sums ? i / (nx * ny) : 0;
+    // index of the cell in the wide offset grid: offset (i - j) = base(i) - base(j) + centre
+    const int wx = 2 * nx - 1, wy = 2 * ny - 1;
+    const int basej = (z * wy + y) * wx + x;
+    const int basei = ((z + nz - 1) * wy + y + ny - 1) * wx + x + nx - 1;
     const float* T = demag + L.demag_off;
-    for (int k = tid; k < 6 * N; k += nthr) Tt[k] = T[k];
+    for (int k = tid; k < 6 * W; k += nthr) Tt[k] = T[k];
     const float* mi = ((n0 & 1) ? buf1 : buf0) + I.state_off;
     V3 m = V3{0.0f, 0.0f, 0.0f};
     V3 u = V3{L.ux, L.uy, L.uz};
+    const float wbits = __int_as_float(basej);
     if (on) {
         m = V3{mi[i], mi[N + i], mi[2 * N + i]};
         if (L.has_axes) u = V3{axes[L.axes_off + i], axes[L.axes_off + N + i], axes[L.axes_off + 2 * N + i]};
-        A[i] = m.x;
-        A[N + i] = m.y;
-        A[2 * N + i] = m.z;
+        A[i] = make_float4(m.x, m.y, m.z, wbits);
     }
     if (tid == 0) acc = accs[inst];
     double* rec = records + I.rec_off;
     // the exchange neighbours are recomputed from (x, y, z) at each use
     // (fewer live registers across the Heun stages)
-    auto nb = [&](const float* St, V3 c) {
+    auto nb = [&](const float4* St, V3 c) {
         const int ixm = x > 0 ? i - 1 : i, ixp = x < nx - 1 ? i + 1 : i;
         const int iym = y > 0 ? i - nx : i, iyp = y < ny - 1 ? i + nx : i;
         const int izm = z > 0 ? i - nx * ny : i, izp = z < nz - 1 ? i + nx * ny : i;
-        return nb_sum(c, V3{St[ixm], St[N + ixm], St[2 * N + ixm]}, V3{St[ixp], St[N + ixp], St[2 * N + ixp]},
-                      V3{St[iym], St[N + iym], St[2 * N + iym]}, V3{St[iyp], St[N + iyp], St[2 * N + iyp]},
-                      V3{St[izm], St[N + izm], St[2 * N + izm]}, V3{St[izp], St[N + izp], St[2 * N + izp]});
+        const float4 a = St[ixm], b = St[ixp], c2 = St[iym], d = St[iyp], e = St[izm], f = St[izp];
+        return nb_sum(c, V3{a.x, a.y, a.z}, V3{b.x, b.y, b.z}, V3{c2.x, c2.y, c2.z}, V3{d.x, d.y, d.z},
+                      V3{e.x, e.y, e.z}, V3{f.x, f.y, f.z});
     };
     // partial sum of the thread's chunk over the state St; chunks 1 .. S-1
     // park theirs in P, the owner keeps chunk 0's in registers
-    auto partial = [&](const float* St) {
+    auto partial = [&](const float4* St) {
         V3 h = V3{0.0f, 0.0f, 0.0f};
-        if (sums) h = demag_partial(St, Tt, x, y, z, nx, ny, N, j0, j1);
+        if (sums)
+            h = wide ? demag_partial_wide(St, Tt, W, basei, j0, j1)
+                     : demag_partial_octant(St, Tt, x, y, z, nx, ny, N, j0, j1);
         if (sums && s > 0) {
             const int p = (s - 1) * N + i;
             P[p] = h.x;
@@ -170,9 +206,7 @@ __global__ __launch_bounds__(kDemagMaxThreads) void k_demag(const InstDev* __res
             hth = thermal_field(L, I.seed, static_cast<uint32_t>(i), n);
             hd = total(hd);
             heun_predict(L, m, nb(A, m), u, hz0, V3{hth.x + hd.x, hth.y + hd.y, hth.z + hd.z}, mp, q);
-            B[i] = mp.x;
-            B[N + i] = mp.y;
-            B[2 * N + i] = mp.z;
+            B[i] = make_float4(mp.x, mp.y, mp.z, wbits);
         }
         __syncthreads();
         hd = partial(B);
@@ -182,9 +216,7 @@ __global__ __launch_bounds__(kDemagMaxThreads) void k_demag(const InstDev* __res
             hd = total(hd);
             m = heun_correct(L, mp, nb(B, mp), u, hz1, V3{hth.x + hd.x, hth.y + hd.y, hth.z + hd.z}, q);
             // nobody reads m_n after the first barrier of the step
-            A[i] = m.x;
-            A[N + i] = m.y;
-            A[2 * N + i] = m.z;
+            A[i] = make_float4(m.x, m.y, m.z, wbits);
             mz = m.z;
         }
         // block sum over whole waves (its barrier also ends the step: A

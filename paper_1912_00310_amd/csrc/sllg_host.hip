@@ -145,12 +145,22 @@ struct Layout {
         max_tiles, max_groups, max_chunks, max_w, ninst_total, max_slabs, xch_words, demag_floats;
 };
 
-// Floats of the demagnetising-tensor table of a grid: six per cell (offsets
-// with non-negative components only).
-int64_t demag_table_floats(const sllg_level& L)
+// The demagnetising-tensor table of a grid holds every cell offset when its
+// six planes fit the LDS beside the kernel's state (wide), else the offsets
+// with non-negative components only (one per cell).
+int64_t demag_wide_offsets(const sllg_level& L)
 {
-    return 6LL * L.nx * L.ny * L.nz;
+    return (int64_t)(2 * L.nx - 1) * (2 * L.ny - 1) * (2 * L.nz - 1);
 }
+bool demag_is_wide(const sllg_level& L)
+{
+    return 6 * sizeof(float) * demag_wide_offsets(L) + kDemagStaticLds <= 160 * 1024;
+}
+int64_t demag_table_offsets(const sllg_level& L)
+{
+    return demag_is_wide(L) ? demag_wide_offsets(L) : (int64_t)L.nx * L.ny * L.nz;
+}
+int64_t demag_table_floats(const sllg_level& L) { return 6 * demag_table_offsets(L); }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -277,7 +287,7 @@ struct sllg_ctx {
     std::vector<int64_t> ev_launches;   // kernel launches inside each timed event pair
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
-    int64_t timed_cells = 0;
+    int64_t timed_cells = 0;            // cell-updates inside the timed event pairs
     int max_lds = 65536;
     int num_cus = 256;
     // HIP graphs of kGraphSteps stream launches per level (the stream kernel
@@ -385,20 +395,24 @@ ldbl second_differences(F fn, ldbl X, ldbl Y, ldbl Z)
     return -(dy(X + 1) - 2 * dy(X) + dy(X - 1)) / (4 * (ldbl)kPi);
 }
 
-// -Ms N for the offsets (dx, dy, dz) >= 0 of an nx x ny x nz grid, six
-// planes of ncell floats (xx yy zz xy xz yz), offset index dx + nx (dy + ny dz).
-// The kernel takes the other offsets from the parities of N: the diagonal is
-// even in each component, N_xy odd in dx and dy, N_xz in dx and dz, N_yz in
-// dy and dz.
+// -Ms N of an nx x ny x nz grid as six planes (xx yy zz xy xz yz) of the
+// table's offsets: every offset (wide; index ((dz + nz-1)(2ny-1) + dy + ny-1)
+// (2nx-1) + dx + nx-1), or those with dx, dy, dz >= 0 (octant; index
+// dx + nx (dy + ny dz)), from which the kernel takes the others by the
+// parities of N: the diagonal is even in each component, N_xy odd in dx and
+// dy, N_xz in dx and dz, N_yz in dy and dz.
 void demag_table(const sllg_level& L, double Ms, std::vector<float>& out)
 {
-    const size_t n = (size_t)L.nx * L.ny * L.nz;
+    const bool wide = demag_is_wide(L);
+    const int ex = wide ? 2 * L.nx - 1 : L.nx, ey = wide ? 2 * L.ny - 1 : L.ny, ez = wide ? 2 * L.nz - 1 : L.nz;
+    const int cx = wide ? L.nx - 1 : 0, cy = wide ? L.ny - 1 : 0, cz = wide ? L.nz - 1 : 0;
+    const size_t n = (size_t)ex * ey * ez;
     out.assign(6 * n, 0.0f);
-    for (int k = 0; k < L.nz; ++k)
-        for (int j = 0; j < L.ny; ++j)
-            for (int i = 0; i < L.nx; ++i) {
-                const ldbl X = i, Y = j, Z = k;
-                const size_t o = ((size_t)k * L.ny + j) * L.nx + i;
+    for (int k = 0; k < ez; ++k)
+        for (int j = 0; j < ey; ++j)
+            for (int i = 0; i < ex; ++i) {
+                const ldbl X = i - cx, Y = j - cy, Z = k - cz;
+                const size_t o = ((size_t)k * ey + j) * ex + i;
                 out[o] = (float)(-Ms * second_differences(nwl_f, X, Y, Z));
                 out[n + o] = (float)(-Ms * second_differences(nwl_f, Y, X, Z));
                 out[2 * n + o] = (float)(-Ms * second_differences(nwl_f, Z, Y, X));
@@ -912,9 +926,14 @@ hipError_t dispatch_lanes(sllg_ctx* C, int l0, int l1, int64_t n0, int64_t ns)
 hipError_t dispatch_demag(sllg_ctx* C, int level, int64_t n0, int64_t ns)
 {
     const LevelHost& h = C->lv[level];
-    hipLaunchKernelGGL(k_demag, dim3((unsigned)h.ninst), dim3((unsigned)demag_block((int)h.ncell)), 0, C->stream,
-                       C->d_insts, h.inst0, C->d_levels, C->d_buf0, C->d_buf1, C->d_axes, C->d_demag, C->d_records,
-                       C->d_accs, C->d_ckpt, C->ckpt_every, n0, ns, C->d_status);
+    const int W = (int)demag_table_offsets(h.in);
+    const size_t lds = 6 * sizeof(float) * (size_t)W;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_demag), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    hipLaunchKernelGGL(k_demag, dim3((unsigned)h.ninst), dim3((unsigned)demag_block((int)h.ncell)), lds, C->stream,
+                       C->d_insts, h.inst0, C->d_levels, C->d_buf0, C->d_buf1, C->d_axes, C->d_demag,
+                       demag_is_wide(h.in) ? 1 : 0, W, C->d_records, C->d_accs, C->d_ckpt, C->ckpt_every, n0, ns,
+                       C->d_status);
     return hipGetLastError();
 }
 
@@ -1223,7 +1242,7 @@ int run_steps(sllg_ctx* C, int64_t nsteps)
             if (timed) {
                 HIP_OK(hipEventRecord(e1, C->stream));
                 C->ev_launches.push_back(nl);
-                C->timed_cells = h.ncell * h.ninst;
+                C->timed_cells += h.ncell * h.ninst * nl;
             }
             k -= nl;
         }
@@ -1248,7 +1267,7 @@ int run_steps(sllg_ctx* C, int64_t nsteps)
             if (timed) {
                 HIP_OK(hipEventRecord(e1, C->stream));
                 C->ev_launches.push_back(ns);   // one launch covers ns steps; report per step
-                C->timed_cells = h.ncell * h.ninst;
+                C->timed_cells += h.ncell * h.ninst * ns;
             }
             HIP_OK(fold_slabs(C, l, h.step, ns));
             h.step += ns;
@@ -1274,7 +1293,7 @@ int run_steps(sllg_ctx* C, int64_t nsteps)
             if (time_this) {
                 HIP_OK(hipEventRecord(e1, C->stream));
                 C->ev_launches.push_back(1);
-                C->timed_cells = h.ncell * h.ninst * ns;
+                C->timed_cells += h.ncell * h.ninst * ns;
             }
             h.step += ns;
             k -= ns;
@@ -1311,7 +1330,7 @@ int run_steps(sllg_ctx* C, int64_t nsteps)
                 C->ev_launches.push_back(1);
                 int64_t cells = 0;
                 for (int l = l0; l < l1; ++l) cells += C->lv[l].ninst;
-                C->timed_cells = cells * ns;
+                C->timed_cells += cells * ns;
             }
             for (int l = l0; l < l1; ++l) C->lv[l].step += ns;
             k -= ns;
@@ -1339,7 +1358,7 @@ int run_steps(sllg_ctx* C, int64_t nsteps)
                 C->ev_launches.push_back(1);
                 int64_t cells = 0;
                 for (int l : rs.levels) cells += C->lv[l].ncell * C->lv[l].ninst;
-                C->timed_cells = cells * ns;
+                C->timed_cells += cells * ns;
             }
             for (int l : rs.levels) C->lv[l].step += ns;
             k -= ns;
@@ -2045,7 +2064,8 @@ int sllg_level_kernel(const sllg_ctx* C, int32_t level, char* name, int32_t cap)
     } else if (h.plan == kPlanLanes) {
         snprintf(buf, sizeof(buf), "k_lanes<%d>", kLanesThreads);
     } else if (h.plan == kPlanDemag) {
-        snprintf(buf, sizeof(buf), "k_demag %dx%d", demag_chunks((int)h.ncell), (int)h.ncell);
+        snprintf(buf, sizeof(buf), "k_demag %dx%d %s", demag_chunks((int)h.ncell), (int)h.ncell,
+                 demag_is_wide(h.in) ? "wide" : "octant");
     } else {
         for (const auto& rs : C->res_sets)
             if (std::find(rs.levels.begin(), rs.levels.end(), level) != rs.levels.end())
@@ -2272,6 +2292,7 @@ int sllg_set_timing(sllg_ctx* C, int32_t on)
     C->timing = on > 0 ? on : 0;
     C->ev_used = 0;
     C->ev_launches.clear();
+    C->timed_cells = 0;
     C->unit_counter = 0;
     return SLLG_OK;
 }
@@ -2291,9 +2312,10 @@ int sllg_kernel_time(sllg_ctx* C, double* mean_ms, int64_t* launches, int64_t* c
     }
     if (mean_ms) *mean_ms = nl ? tot / nl : 0.0;
     if (launches) *launches = nl;
-    if (cells_per_launch) *cells_per_launch = C->timed_cells;
+    if (cells_per_launch) *cells_per_launch = nl ? C->timed_cells / nl : 0;
     C->ev_used = 0;
     C->ev_launches.clear();
+    C->timed_cells = 0;
     return SLLG_OK;
 }
 
