@@ -149,9 +149,11 @@ def fit_coarse_to_fine(material: dict, fine: dict, coarse: dict, fit=("K", "A"),
 
 
 if __name__ == "__main__":
-    # The b = 4 rod fitted to the b = 1 rod: Hmax = 500 Oe cosine sweep at
-    # 250 Oe/ns, alpha = 1, easy axes in a 5 degree cone, T = 310 K
-    # (python -m paper_1912_00310_amd.fit from the repository root).
+    # The b = 4 rod (or with --b2 the 1344-cell b = 2 rod) fitted to the b = 1
+    # rod: Hmax = 500 Oe cosine sweep at 250 Oe/ns, alpha = 1, easy axes in a
+    # 5 degree cone, T = 310 K; --delta fits the Eq. 13 weight to the
+    # remanence as well (python -m paper_1912_00310_amd.fit [--b2] [--delta]
+    # from the repository root).
     import json
     import sys
 
@@ -160,7 +162,10 @@ if __name__ == "__main__":
     mat = dict(W.BASE_MATERIAL, Hmax_Oe=500.0, sweep_Oe_per_ns=250.0, wave="cosine")
     common = dict(seed_base=1, alpha=1.0, cone_deg=5.0, axis_seed=11)
     fine = dict(common, nx=8, ny=24, nz=56, b=1.0, n_real=8, dt_s=1e-15, record_every=1000)
-    coarse = dict(common, nx=2, ny=6, nz=14, b=4.0, n_real=64, dt_s=5e-15, record_every=1)
+    if "--b2" in sys.argv:
+        coarse = dict(common, nx=4, ny=12, nz=28, b=2.0, n_real=64, dt_s=5e-15, record_every=1)
+    else:
+        coarse = dict(common, nx=2, ny=6, nz=14, b=4.0, n_real=64, dt_s=5e-15, record_every=1)
     keys = ("S_phys", "S_se", "Hc_phys", "Hc_se", "Mr_phys")
     rule = Sim(mat, [coarse])
     rule.run_sweep()
@@ -168,7 +173,8 @@ if __name__ == "__main__":
     rule.close()
     sf, start, vals, hist = fit_coarse_to_fine(mat, fine, coarse, fit_delta="--delta" in sys.argv,
                                                log=lambda s: print(s, file=sys.stderr, flush=True))
-    print(json.dumps({"fine_b1": {k: sf[k] for k in keys}, "coarse_b4_rule": {k: sr[k] for k in keys},
+    print(json.dumps({"fine_b1": {k: sf[k] for k in keys}, "coarse_b": coarse["b"],
+                      "coarse_rule": {k: sr[k] for k in keys},
                       "rule": start, "fitted": vals,
                       "history": [{k: h[k] for k in ("K", "A", "S_phys", "Hc_phys", "Mr_phys", "delta", "err")}
                                   for h in hist]}))
