@@ -190,11 +190,19 @@ int shape_rows(const sllg_level& L, const Shape& s)
 }
 
 // Dynamic LDS of a k_rows2 tile: two m_n planes (predicted rows + 2) and
-// two m' planes (predicted rows), one float4 per cell.
+// two m' planes (predicted rows), one float4 per cell.  With one cell per
+// thread the planes sit at fixed strides: 2 tx cells for m_n, tx for m'.
 size_t rows2_lds(const sllg_level& L, const Shape& s)
 {
+    if (s.ty == 1) return 16 * (size_t)6 * s.tx;
     const int R = std::min(shape_rows(L, s), L.ny);
     return 16 * (size_t)(2 * (R + 2) + 2 * R) * L.nx;
+}
+
+// Cells of an m_n plane of a k_rows2 tile (predicted rows + 2).
+int64_t rows2_plane_cells(const sllg_level& L, const Shape& s)
+{
+    return (int64_t)(std::min(shape_rows(L, s), L.ny) + 2) * L.nx;
 }
 
 bool shape_fits(const sllg_level& L, const Shape& s)
@@ -205,6 +213,7 @@ bool shape_fits(const sllg_level& L, const Shape& s)
     if (s.kind == 2) {
         if (R < L.ny && 2 * L.nx > s.tx) return false;   // the two extra rows need 2 nx threads
         if (rows2_lds(L, s) > 160 * 1024 - 1024) return false;
+        if (s.ty == 1 && rows2_plane_cells(L, s) > 2 * s.tx) return false;   // the fixed m_n stride
     }
     return !row_windows(L.ny, R).empty();
 }

@@ -7,23 +7,24 @@
 // region are dealt to the threads in row-major order, K per thread, and a
 // thread keeps its cells' z-columns in registers: m_n of planes p, p+1 and
 // p+2 (the load of p+3 is issued during plane p), the easy axes of p-1, p and
-// p+1, q and H_th of the plane before, and m' of planes p, p-1 and p-2.  The
-// three-plane columns rotate by renaming: the plane loop is unrolled three
-// times.  LDS holds only x-y planes, one float4 per cell: m_n of planes p and
-// p - 1 (the predicted rows plus the rows py0 - 1 and py1, which the first
-// 2*nx threads load two planes ahead) and m' of planes p and p - 1; every
-// buffer is written once per plane and read by other threads only until the
-// next barrier, so one barrier per plane suffices, and a thread reads its
-// own column's previous plane back from LDS.  Global accesses are buffer
-// instructions with 32-bit offsets.  At plane p the workgroup
+// p+1, q and H_th of the plane before, m' of planes p, p-1 and p-2, and the
+// extra rows (below) of planes p+1 .. p+3.  The three-plane columns rotate by
+// renaming and the LDS buffers alternate, so the plane loop is unrolled six
+// times.  LDS holds only x-y planes, one 16-byte slot per cell: m_n of planes
+// p and p - 1 (the predicted rows plus the rows py0 - 1 and py1, which the
+// first 2*nx threads load three planes ahead) and m' of planes p and p - 1;
+// every buffer is written once per plane and read by other threads only
+// until the next barrier, so one barrier per plane suffices, and a thread
+// reads its own column's previous plane back from LDS.  Global accesses are
+// buffer instructions with 32-bit offsets.  At plane p the workgroup
 //   1. writes m_n(p) to LDS and waits at the barrier,
 //   2. predicts plane p from LDS (x-y) and registers (z),
 //   3. writes m'(p) to the other LDS buffer, and the extra rows of plane
 //      p + 1 into the m_n buffer of plane p - 1,
 //   4. corrects plane p - 1 from m'(p - 1) in LDS (x-y) and registers (z),
 //      storing m_{n+1},
-//   5. issues the loads of plane p + 3, of the axes of plane p + 2 and of
-//      the extra rows of plane p + 2.
+//   5. issues the loads of the extra rows of plane p + 4, of plane p + 3 and
+//      of the axes of plane p + 2.
 // The planes z0 - 1 and z0 + nzt are predicted for the window cells only
 // (their m' is needed only as a vertical neighbour).  Workgroups are dealt to
 // the XCDs so that each XCD runs a contiguous part of the tile list.
@@ -81,9 +82,17 @@ __global__ __launch_bounds__(NT) void k_rows2(
     const int pz0 = max(z0 - 1, 0), pz1 = min(zend, nz - 1);
     const int LC = (py1 - py0 + 2) * nx;   // LDS cells of an m_n plane (rows py0 - 1 .. py1)
     const int PC = (py1 - py0) * nx;       // predicted cells
-    // cells as float4 (x, y, z, unused): one 16-byte LDS access per neighbour
-    float4* const Mn0 = lds_rows2;            // [2][LC]: m_n of planes p (buffer p & 1) and p - 1
-    float4* const Mp0 = lds_rows2 + 2 * LC;   // [2][PC]: m' of planes p (buffer p & 1) and p - 1
+    // cells in 16-byte slots (x, y, z, unused): one LDS access per neighbour
+    // Buffer (p - pz0) & 1 of each pair holds plane p.  With one cell per
+    // thread the buffers sit at fixed strides (an m_n plane holds at most
+    // 2 NT cells: the host refuses tiles with more), so that with the plane
+    // loop unrolled six times every LDS access is a per-thread offset plus an
+    // immediate; with two cells per thread they are packed.
+    constexpr bool FIXED = K == 1;
+    const int SN = FIXED ? 2 * NT : LC;        // stride of the m_n buffers (cells)
+    const int SP = FIXED ? NT : PC;            // stride of the m' buffers
+    float4* const Mn0 = lds_rows2;             // [2][SN]: m_n of planes p and p - 1
+    float4* const Mp0 = lds_rows2 + 2 * SN;    // [2][SP]: m' of planes p and p - 1
     const float hz0 = static_cast<float>(L.hz_amp * wave_at(L, n));
     const float hz1 = static_cast<float>(L.hz_amp * wave_at(L, n + 1));
     const bool do_ckpt = (ckpt != nullptr) && ckpt_every > 0 && (n % ckpt_every) == 0;
@@ -177,7 +186,14 @@ __global__ __launch_bounds__(NT) void k_rows2(
 #pragma unroll
     for (int j = 0; j < K; ++j) gb[j] = static_cast<uint32_t>(ii[j] + gofs) * 4u;
     const uint32_t ex_gb = static_cast<uint32_t>(ex_gc) * 4u;
-    auto f4 = [](V3 v) { return make_float4(v.x, v.y, v.z, 0.0f); };
+    // a cell to LDS: x, y, z of its 16-byte slot (one 12-byte store; the
+    // fourth word is never read)
+    auto put = [](float4* slot, V3 v) {
+        float* q = static_cast<float*>(__builtin_assume_aligned(slot, 16));
+        q[0] = v.x;
+        q[1] = v.y;
+        q[2] = v.z;
+    };
     auto v34 = [](float4 v) { return V3{v.x, v.y, v.z}; };
 
     auto xm = [&](int i, int e) { return (e & 1) ? i - 1 : i; };
@@ -197,9 +213,11 @@ __global__ __launch_bounds__(NT) void k_rows2(
 #pragma unroll
         for (int k = 0; k < 3; ++k) M[k][j] = U[k][j] = Q[k][j] = HT[k][j] = V3{0, 0, 0};
         MP[0][j] = MP[1][j] = MP[2][j] = V3{0, 0, 0};
-        if (pz0 > 0 && on[j]) {
-            // plane pz0 - 1 of the own column, the lower neighbour of the first plane
-            Mn0[((pz0 - 1) & 1) * LC + ii[j] + nx] = f4(ld(pz0 - 1, gb[j]));
+        if (on[j]) {
+            // plane pz0 - 1 of the own column, the lower neighbour of the
+            // first plane; at the bottom of the grid plane 0 itself, so that
+            // the missing neighbour is the cell (no select in the loop)
+            put(&Mn0[SN + ii[j] + nx], ld(max(pz0 - 1, 0), gb[j]));
         }
         M[0][j] = ld(pz0, gb[j]);
         M[1][j] = ld(pz0 + 1, gb[j]);
@@ -210,29 +228,32 @@ __global__ __launch_bounds__(NT) void k_rows2(
         }
     }
     // the extra rows of plane p go to LDS during plane p - 1 (below), loaded
-    // at the end of plane p - 2; those of the first plane here
-    if (ex) Mn0[(pz0 & 1) * LC + ex_li] = f4(ld(pz0, ex_gb));
-    V3 e_next = ld(pz0 + 1, ex_gb);
+    // at the end of plane p - 3; those of the first plane here
+    if (ex) put(&Mn0[ex_li], ld(pz0, ex_gb));
+    // extra rows of the planes p + 1, p + 2, p + 3 (slot PH holds p + 1)
+    V3 E[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) E[k] = ld(min(pz0 + 1 + k, pz1), ex_gb);
 
     float msum = 0.0f;
     const int zlast = min(pz1 + 1, nz - 1);    // the last plane of m_n the tile reads
     const int plast = zend == nz ? nz : pz1;   // the last plane holds only a corrector when zend = nz
     auto plane = [&](auto phase, const int p) {
-        constexpr int PH = decltype(phase)::value;
+        constexpr int PH = decltype(phase)::value % 3;
         constexpr int P1 = (PH + 1) % 3, P2 = (PH + 2) % 3;
+        constexpr int b = decltype(phase)::value & 1;   // buffer of plane p
         const bool predict = p <= pz1;
         const bool halo_plane = p < z0 || p >= zend;
-        const int b = p & 1;
-        float4* Mn = Mn0 + b * LC;
-        const float4* Mo = Mn0 + (b ^ 1) * LC;                      // m_n of plane p - 1
-        float4* Mp = Mp0 + b * PC;
-        const float4* Mq = Mp0 + (b ^ 1) * PC;                      // m' of plane p - 1
+        float4* Mn = Mn0 + b * SN;
+        const float4* Mo = Mn0 + (b ^ 1) * SN;                      // m_n of plane p - 1
+        float4* Mp = Mp0 + b * SP;
+        const float4* Mq = Mp0 + (b ^ 1) * SP;                      // m' of plane p - 1
         // ---- 1. m_n(p) to LDS
         if (predict) {
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 if (!on[j]) continue;
-                Mn[ii[j] + nx] = f4(M[PH][j]);
+                put(&Mn[ii[j] + nx], M[PH][j]);
             }
         }
         lds_barrier();
@@ -252,24 +273,26 @@ __global__ __launch_bounds__(NT) void k_rows2(
                 // meanwhile would spill)
                 const V3 n_xm = v34(Mn[xm(l, e)]), n_xp = v34(Mn[xp(l, e)]);
                 const V3 n_ym = v34(Mn[ym(l, e)]), n_yp = v34(Mn[yp(l, e)]);
-                const V3 n_zm = p > 0 ? v34(Mo[l]) : m;
+                // (below plane 0 the buffer holds plane 0; above nz - 1 the
+                // clamped load of M[P1] holds plane nz - 1: the cell itself)
+                const V3 n_zm = v34(Mo[l]);
                 HT[PH][j] = thermal_field(Lc, I.seed, cell, n);
-                exs = nb_sum(m, n_xm, n_xp, n_ym, n_yp, n_zm, p < nz - 1 ? M[P1][j] : m);
+                exs = nb_sum(m, n_xm, n_xp, n_ym, n_yp, n_zm, M[P1][j]);
             } else {
                 exs = nb_sum(m, v34(Mn[xm(l, e)]), v34(Mn[xp(l, e)]), v34(Mn[ym(l, e)]), v34(Mn[yp(l, e)]),
-                             p > 0 ? v34(Mo[l]) : m, p < nz - 1 ? M[P1][j] : m);
+                             v34(Mo[l]), M[P1][j]);
                 HT[PH][j] = thermal_field(Lc, I.seed, cell, n);
             }
             heun_predict(Lc, m, exs, AXES ? U[P1][j] : u0, hz0, HT[PH][j], MP[PH][j], Q[PH][j]);
-            Mp[ii[j]] = f4(MP[PH][j]);
+            put(&Mp[ii[j]], MP[PH][j]);
         }
         // ---- the extra rows of plane p + 1 into the m_n buffer of plane
         //      p - 1, whose extra rows nobody reads after the barrier above.
         //      (Before the corrector's stores, so that the wait for the load
         //      does not include them; the empty asm uses the loaded values in
         //      every wave, so that the wait is taken here whichever lanes store.)
-        asm volatile("" ::"v"(e_next.x), "v"(e_next.y), "v"(e_next.z));
-        if (ex && p + 1 <= pz1) Mn0[(b ^ 1) * LC + ex_li] = f4(e_next);
+        asm volatile("" ::"v"(E[PH].x), "v"(E[PH].y), "v"(E[PH].z));
+        if (ex && p + 1 <= pz1) put(&Mn0[(b ^ 1) * SN + ex_li], E[PH]);
         // ---- 4. corrector at plane p - 1
         const int cz = p - 1;
         if (cz >= z0 && cz < zend) {
@@ -286,9 +309,10 @@ __global__ __launch_bounds__(NT) void k_rows2(
                 if (do_ckpt) st3(r_ck, cz, gb[j], v34(Mo[ii[j] + nx]));
             }
         }
-        // ---- 5. loads of plane p + 3 into the slot of plane p, of the axes of
-        //         plane p + 2 into the slot of plane p - 1 and of the extra
-        //         rows of plane p + 2
+        // ---- 5. loads of the extra rows of plane p + 4 into their slot of
+        //         plane p + 1, of plane p + 3 into the slot of plane p and of
+        //         the axes of plane p + 2 into the slot of plane p - 1
+        E[PH] = ldc(min(p + 4, pz1), ex_gb);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             // The loads are unconditional, so that the compiler can count the
@@ -298,17 +322,22 @@ __global__ __launch_bounds__(NT) void k_rows2(
             M[PH][j] = ldc(min(p + 3, zlast), gb[j]);
             if (AXES) U[PH][j] = lduc(min(p + 2, pz1), gb[j]);
         }
-        e_next = ldc(min(p + 2, pz1), ex_gb);
     };
     // the first loads complete before the loop, so that the wait counts in
     // the loop follow its own loads only
     __builtin_amdgcn_s_waitcnt(0);
-    for (int p = pz0; p <= plast; p += 3) {
+    // Whole groups of six planes (the register slots rotate with period 3,
+    // the LDS buffers with period 2), so that the loop has one path per trip
+    // and the wait counts of the loads stay exact: a plane past plast
+    // predicts and corrects nothing (p > pz1 and p - 1 >= zend), and its
+    // loads repeat the last plane.
+    for (int p = pz0; p <= plast; p += 6) {
         plane(std::integral_constant<int, 0>{}, p);
-        if (p + 1 > plast) break;
         plane(std::integral_constant<int, 1>{}, p + 1);
-        if (p + 2 > plast) break;
         plane(std::integral_constant<int, 2>{}, p + 2);
+        plane(std::integral_constant<int, 3>{}, p + 3);
+        plane(std::integral_constant<int, 4>{}, p + 4);
+        plane(std::integral_constant<int, 5>{}, p + 5);
     }
 
     const double tot = block_sum<NT>(msum, red);
