@@ -1454,20 +1454,16 @@ int tune_stream(sllg_ctx* C, int level)
     hipEvent_t e0, e1;
     HIP_OK(hipEventCreate(&e0));
     HIP_OK(hipEventCreate(&e1));
-    double best_t = 1e30;
-    std::pair<int, int> best = {h.shape, h.tz};
-    const int reps = 6;
-    for (auto c : cands) {
+    // ms per step of one candidate: warm-up, then the better of `runs` runs
+    // of `reps` launches; the step counters are reset afterwards
+    auto time_cand = [&](std::pair<int, int> c, int reps, int runs, double* out) -> int {
         h.shape = c.first;
         h.tz = c.second;
         int rc = replan(C);
         if (rc) return rc;
-        // warm-up then timed steps, the better of two runs (candidates a few
-        // per cent apart are told apart despite launch jitter); state is
-        // reset afterwards
         for (int r = 0; r < 2; ++r) HIP_OK(dispatch_stream(C, level));
         float ms = 1e30f;
-        for (int run = 0; run < 2; ++run) {
+        for (int run = 0; run < runs; ++run) {
             HIP_OK(hipEventRecord(e0, C->stream));
             for (int r = 0; r < reps; ++r) HIP_OK(dispatch_stream(C, level));
             HIP_OK(hipEventRecord(e1, C->stream));
@@ -1476,23 +1472,51 @@ int tune_stream(sllg_ctx* C, int level)
             HIP_OK(hipEventElapsedTime(&t, e0, e1));
             ms = std::min(ms, t);
         }
+        HIP_OK(hipMemsetAsync(C->d_steps, 0, sizeof(int64_t) * C->lv.size(), C->stream));
+        HIP_OK(hipMemsetAsync(C->d_inst_cnt, 0, sizeof(uint32_t) * C->lay.ninst_total, C->stream));
+        *out = ms / reps;
+        return SLLG_OK;
+    };
+    // every candidate briefly (the better of two runs of 6 launches), then
+    // the candidates within 5 % of the best again with runs four times as
+    // long, so that shapes a few per cent apart are told apart despite launch
+    // jitter
+    std::vector<std::pair<double, std::pair<int, int>>> timed;
+    for (auto c : cands) {
+        double t = 0;
+        int rc = time_cand(c, 6, 2, &t);
+        if (rc) return rc;
         if (g_options & SLLG_OPT_VERBOSE)
             fprintf(stderr, "tune level %d: shape %d (%d,%d,%d,%d) tz %d tiles %d: %.2f us/step\n", level,
                     c.first, kShapes[c.first].kind, kShapes[c.first].tx, kShapes[c.first].ty,
-                    kShapes[c.first].pz, c.second, h.ntiles, 1000.0 * ms / reps);
-        if (ms < best_t) {
-            best_t = ms;
-            best = c;
+                    kShapes[c.first].pz, c.second, h.ntiles, 1000.0 * t);
+        timed.push_back({t, c});
+    }
+    std::sort(timed.begin(), timed.end());
+    double best_t = timed[0].first;
+    std::pair<int, int> best = timed[0].second;
+    const double lead = timed[0].first;
+    if (timed.size() > 1 && timed[1].first <= 1.05 * lead) {
+        best_t = 1e30;
+        for (size_t i = 0; i < timed.size() && i < 4 && timed[i].first <= 1.05 * lead; ++i) {
+            double t = 0;
+            int rc = time_cand(timed[i].second, 24, 3, &t);
+            if (rc) return rc;
+            if (g_options & SLLG_OPT_VERBOSE)
+                fprintf(stderr, "tune level %d: finalist shape %d tz %d: %.2f us/step\n", level,
+                        timed[i].second.first, timed[i].second.second, 1000.0 * t);
+            if (t < best_t) {
+                best_t = t;
+                best = timed[i].second;
+            }
         }
-        HIP_OK(hipMemsetAsync(C->d_steps, 0, sizeof(int64_t) * C->lv.size(), C->stream));
-        HIP_OK(hipMemsetAsync(C->d_inst_cnt, 0, sizeof(uint32_t) * C->lay.ninst_total, C->stream));
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     h.shape = best.first;
     h.tz = best.second;
     g_tuned[key] = best;
-    g_tuned_ms[key] = best_t / reps;
+    g_tuned_ms[key] = best_t;
     return SLLG_OK;
 }
 
@@ -1517,6 +1541,30 @@ int tune_slab(sllg_ctx* C, int level, double* best_ms)
     HIP_OK(hipEventCreate(&e0));
     HIP_OK(hipEventCreate(&e1));
     int best_k = -1, best_tz = 0;
+    // ms per step of the candidate set up in h: the better of `runs` launches
+    // of `steps` steps after a short warm-up; false if its bounded waits gave
+    // up (the time then means nothing; the status word is cleared)
+    auto time_slab = [&](int steps, int runs, float* ms, bool* ok) -> int {
+        h.step = 0;
+        HIP_OK(dispatch_slab(C, level, 0, 16));
+        *ms = 1e30f;
+        for (int rep = 0; rep < runs; ++rep) {
+            HIP_OK(hipEventRecord(e0, C->stream));
+            HIP_OK(dispatch_slab(C, level, 16 + rep * steps, steps));
+            HIP_OK(hipEventRecord(e1, C->stream));
+            HIP_OK(hipEventSynchronize(e1));
+            float t = 0;
+            HIP_OK(hipEventElapsedTime(&t, e0, e1));
+            *ms = std::min(*ms, t / steps);
+        }
+        int st[4] = {0, 0, 0, 0};
+        HIP_OK(hipMemcpyAsync(st, C->d_status, sizeof(st), hipMemcpyDeviceToHost, C->stream));
+        HIP_OK(hipStreamSynchronize(C->stream));
+        *ok = !(st[0] & 2);
+        if (!*ok) HIP_OK(hipMemsetAsync(C->d_status, 0, sizeof(int) * 4, C->stream));
+        return SLLG_OK;
+    };
+    std::vector<std::tuple<float, int, int>> timed;   // ms per step, kernel, tz
     for (int ki = 0; ki < kNumSlabKernels; ++ki) {
         const int NPP = kSlabKernels[ki].nt / P;
         if (NPP < 1) continue;
@@ -1533,28 +1581,14 @@ int tune_slab(sllg_ctx* C, int level, double* best_ms)
             if (rc) return rc;
             bool fits = false;
             if (dispatch_slab(C, level, 0, 1, true, &fits) != hipSuccess || !fits) continue;
-            h.step = 0;
-            HIP_OK(dispatch_slab(C, level, 0, 16));
             // the better of two launches of 256 steps: shapes a few per cent
             // apart are told apart despite the launch overhead and its jitter
-            constexpr int kTuneSteps = 256;
-            float ms = 1e30f;
-            for (int rep = 0; rep < 2; ++rep) {
-                HIP_OK(hipEventRecord(e0, C->stream));
-                HIP_OK(dispatch_slab(C, level, 16 + rep * kTuneSteps, kTuneSteps));
-                HIP_OK(hipEventRecord(e1, C->stream));
-                HIP_OK(hipEventSynchronize(e1));
-                float t = 0;
-                HIP_OK(hipEventElapsedTime(&t, e0, e1));
-                ms = std::min(ms, t);
-            }
-            // a candidate whose bounded waits gave up is dropped (its time
-            // means nothing) and the status word cleared for the next one
-            int st[4] = {0, 0, 0, 0};
-            HIP_OK(hipMemcpyAsync(st, C->d_status, sizeof(st), hipMemcpyDeviceToHost, C->stream));
-            HIP_OK(hipStreamSynchronize(C->stream));
-            if (st[0] & 2) {
-                HIP_OK(hipMemsetAsync(C->d_status, 0, sizeof(int) * 4, C->stream));
+            // (a candidate whose bounded waits gave up is dropped)
+            float ms = 0;
+            bool ok = false;
+            rc = time_slab(256, 2, &ms, &ok);
+            if (rc) return rc;
+            if (!ok) {
                 if (g_options & SLLG_OPT_VERBOSE)
                     fprintf(stderr, "tune level %d: slab kernel %d tz %d dropped (exchange timed out)\n", level,
                             ki, tz);
@@ -1562,12 +1596,39 @@ int tune_slab(sllg_ctx* C, int level, double* best_ms)
             }
             if (g_options & SLLG_OPT_VERBOSE)
                 fprintf(stderr, "tune level %d: slab kernel %d (%d,%d) tz %d slabs %d: %.3f us/step\n", level, ki,
-                        kSlabKernels[ki].nt, kSlabKernels[ki].k, tz, h.nslab, 1000.0 * ms / kTuneSteps);
-            if (ms / kTuneSteps < *best_ms) {
-                *best_ms = ms / kTuneSteps;
-                best_k = ki;
-                best_tz = tz;
+                        kSlabKernels[ki].nt, kSlabKernels[ki].k, tz, h.nslab, 1000.0 * ms);
+            timed.push_back(std::make_tuple(ms, ki, tz));
+        }
+    }
+    // the candidates within 5 % of the best again, with launches four times
+    // as long
+    std::sort(timed.begin(), timed.end());
+    if (!timed.empty()) {
+        const float lead = std::get<0>(timed[0]);
+        const bool close = timed.size() > 1 && std::get<0>(timed[1]) <= 1.05f * lead;
+        for (size_t i = 0; i < timed.size() && i < 3; ++i) {
+            float ms = std::get<0>(timed[i]);
+            if (close) {
+                if (ms > 1.05f * lead) break;
+                h.plan = kPlanSlab;
+                h.slab_kernel = std::get<1>(timed[i]);
+                h.slab_tz = std::get<2>(timed[i]);
+                int rc = replan(C);
+                if (rc) return rc;
+                bool ok = false;
+                rc = time_slab(1024, 2, &ms, &ok);
+                if (rc) return rc;
+                if (!ok) continue;
+                if (g_options & SLLG_OPT_VERBOSE)
+                    fprintf(stderr, "tune level %d: finalist slab kernel %d tz %d: %.3f us/step\n", level,
+                            std::get<1>(timed[i]), std::get<2>(timed[i]), 1000.0 * ms);
             }
+            if (ms < *best_ms) {
+                *best_ms = ms;
+                best_k = std::get<1>(timed[i]);
+                best_tz = std::get<2>(timed[i]);
+            }
+            if (!close) break;
         }
     }
     (void)hipEventDestroy(e0);
