@@ -7,10 +7,13 @@
 // cell i is Hd_i = sum_j T(r_i - r_j) m_j with T = -Ms N the demagnetising
 // tensor of two uniformly magnetised cubes.  The host tabulates T in one of
 // two forms (six planes xx yy zz xy xz yz):
-//   - wide: every offset of the grid, (2nx-1)(2ny-1)(2nz-1) of them, offset
-//     index ((dz+nz-1)(2ny-1) + dy+ny-1)(2nx-1) + dx+nx-1, used when it fits
-//     the LDS: the index of a pair is base(i) - base(j) with base(j) stored
-//     beside m_j, one subtraction per pair;
+//   - wide: every offset of the grid, in rows of wx >= 2nx-1 and planes of
+//     wy >= 2ny-1 rows (2nz-1 planes), offset index
+//     ((dz+nz-1) wy + dy+ny-1) wx + dx+nx-1, used when it fits the LDS: the
+//     index of a pair is base(i) - base(j) with base(j) stored beside m_j,
+//     one subtraction per pair.  The host pads wx and wy so that the 64
+//     lanes of a wave, which read the table at 64 different offsets, spread
+//     over the LDS banks;
 //   - octant: the offsets with dx, dy, dz >= 0 only (one per cell), for the
 //     larger grids: N is even in every component of the offset on its
 //     diagonal, N_xy odd in dx and dy (even in dz), N_xz odd in dx and dz,
@@ -108,13 +111,14 @@ __device__ __forceinline__ V3 demag_partial_octant(const float4* __restrict__ S,
 constexpr size_t kDemagStaticLds =
     2 * sizeof(float4) * kDemagMaxCells + 3 * sizeof(float) * kDemagMaxThreads + 8 * (kDemagMaxThreads / 64) + 128;
 
-// wide != 0: the table holds every offset (W of them); else the octant
-// table (W = N).
+// wide != 0: the table holds every offset (W = wx wy (2nz-1) of them, rows of
+// wx, planes of wy rows); else the octant table (W = N).
 __global__ __launch_bounds__(kDemagMaxThreads) void k_demag(const InstDev* __restrict__ insts, int inst0,
                                                            const LevelDev* __restrict__ levels,
                                                            float* __restrict__ buf0, float* __restrict__ buf1,
                                                            const float* __restrict__ axes,
                                                            const float* __restrict__ demag, int wide, int W,
+                                                           int wx, int wy,
                                                            double* __restrict__ records, AccDev* __restrict__ accs,
                                                            float* __restrict__ ckpt, int ckpt_every, int64_t n0,
                                                            int64_t nsteps, int* __restrict__ status)
@@ -137,7 +141,6 @@ __global__ __launch_bounds__(kDemagMaxThreads) void k_demag(const InstDev* __res
     const int j0 = sums ? s * clen : 0, j1 = sums ? min(N, j0 + clen) : 0;
     const int x = sums ? i % nx : 0, y = sums ? (i / nx) % ny : 0, z = sums ? i / (nx * ny) : 0;
     // index of the cell in the wide offset grid: offset (i - j) = base(i) - base(j) + centre
-    const int wx = 2 * nx - 1, wy = 2 * ny - 1;
     const int basej = (z * wy + y) * wx + x;
     const int basei = ((z + nz - 1) * wy + y + ny - 1) * wx + x + nx - 1;
     const float* T = demag + L.demag_off;

@@ -148,13 +148,89 @@ struct Layout {
 // The demagnetising-tensor table of a grid holds every cell offset when its
 // six planes fit the LDS beside the kernel's state (wide), else the offsets
 // with non-negative components only (one per cell).
+//
+// Row and plane strides of the wide table: at least 2nx - 1 and 2ny - 1,
+// padded so that the table reads of a wave (lane i reads offset base(i) -
+// base(j), every lane a different address) fall on as few addresses per LDS
+// bank as the budget allows.  The cost model follows k_demag's threads
+// (thread s N + i sums chunk s for cell i): for every wave and a few steps j
+// of the chunk loop, the largest number of distinct addresses on one of 32
+// banks of 4 bytes, for each half-wave of 32 lanes.  (This rule ranked the
+// measured strides of the 2x6x14 rod in their order of speed; a 64-lane rule
+// over 32 or 64 banks did not.)
+struct WideDims {
+    int wx, wy;
+};
+WideDims demag_wide_dims(const sllg_level& L)
+{
+    const int nx = L.nx, ny = L.ny, nz = L.nz, N = nx * ny * nz;
+    const WideDims tight{2 * nx - 1, 2 * ny - 1};
+    // chosen once per grid shape (the search takes some milliseconds)
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int>, WideDims> cache;
+    const auto key = std::make_tuple(nx, ny, nz);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    auto fits = [&](int wx, int wy) {
+        return 6 * sizeof(float) * (size_t)wx * wy * (2 * nz - 1) + kDemagStaticLds <= 160 * 1024;
+    };
+    const int clen = demag_chunk_len(N), S = demag_chunks(N), waves = demag_block(N) / 64;
+    auto cost = [&](int wx, int wy) {
+        int64_t c = 0;
+        std::vector<int> addr(32), hits;
+        for (int w = 0; w < waves; ++w)
+            for (int k = 0; k < clen; k += std::max(1, clen / 4))
+                for (int half = 0; half < 2; ++half) {
+                    int na = 0;
+                    for (int l = 32 * half; l < 32 * half + 32; ++l) {
+                        const int t = 64 * w + l, s = t / N, i = t - s * N;
+                        const int j = s * clen + k;
+                        if (s >= S || j >= N || (j >= (s + 1) * clen)) continue;
+                        const int bi = ((i / (nx * ny)) * wy + (i / nx) % ny) * wx + i % nx;
+                        const int bj = ((j / (nx * ny)) * wy + (j / nx) % ny) * wx + j % nx;
+                        addr[na++] = bi - bj;
+                    }
+                    std::sort(addr.begin(), addr.begin() + na);
+                    na = (int)(std::unique(addr.begin(), addr.begin() + na) - addr.begin());
+                    hits.assign(32, 0);
+                    int worst = 0;
+                    for (int a = 0; a < na; ++a) worst = std::max(worst, ++hits[((addr[a] % 32) + 32) % 32]);
+                    c += worst;
+                }
+        return c;
+    };
+    WideDims best = tight;
+    if (N > kDemagMaxCells || !fits(tight.wx, tight.wy)) {
+        std::lock_guard<std::mutex> g(mu);
+        cache[key] = best;
+        return best;
+    }
+    int64_t best_c = cost(tight.wx, tight.wy);
+    for (int wx = tight.wx; wx <= tight.wx + 8; ++wx)
+        for (int wy = tight.wy; wy <= tight.wy + 24; ++wy) {
+            if (!fits(wx, wy)) continue;
+            const int64_t c = cost(wx, wy);
+            if (c < best_c || (c == best_c && wx * wy < best.wx * best.wy)) {
+                best_c = c;
+                best = WideDims{wx, wy};
+            }
+        }
+    std::lock_guard<std::mutex> g(mu);
+    cache[key] = best;
+    return best;
+}
 int64_t demag_wide_offsets(const sllg_level& L)
 {
-    return (int64_t)(2 * L.nx - 1) * (2 * L.ny - 1) * (2 * L.nz - 1);
+    const WideDims d = demag_wide_dims(L);
+    return (int64_t)d.wx * d.wy * (2 * L.nz - 1);
 }
 bool demag_is_wide(const sllg_level& L)
 {
-    return 6 * sizeof(float) * demag_wide_offsets(L) + kDemagStaticLds <= 160 * 1024;
+    return 6 * sizeof(float) * (size_t)(2 * L.nx - 1) * (2 * L.ny - 1) * (2 * L.nz - 1) + kDemagStaticLds <=
+           160 * 1024;
 }
 int64_t demag_table_offsets(const sllg_level& L)
 {
@@ -405,21 +481,24 @@ ldbl second_differences(F fn, ldbl X, ldbl Y, ldbl Z)
 }
 
 // -Ms N of an nx x ny x nz grid as six planes (xx yy zz xy xz yz) of the
-// table's offsets: every offset (wide; index ((dz + nz-1)(2ny-1) + dy + ny-1)
-// (2nx-1) + dx + nx-1), or those with dx, dy, dz >= 0 (octant; index
+// table's offsets: every offset (wide; index ((dz + nz-1) wy + dy + ny-1) wx
+// + dx + nx-1 with the strides of demag_wide_dims; the padding entries are
+// zero and never read), or those with dx, dy, dz >= 0 (octant; index
 // dx + nx (dy + ny dz)), from which the kernel takes the others by the
 // parities of N: the diagonal is even in each component, N_xy odd in dx and
 // dy, N_xz in dx and dz, N_yz in dy and dz.
 void demag_table(const sllg_level& L, double Ms, std::vector<float>& out)
 {
     const bool wide = demag_is_wide(L);
-    const int ex = wide ? 2 * L.nx - 1 : L.nx, ey = wide ? 2 * L.ny - 1 : L.ny, ez = wide ? 2 * L.nz - 1 : L.nz;
+    const WideDims d = demag_wide_dims(L);
+    const int ex = wide ? d.wx : L.nx, ey = wide ? d.wy : L.ny, ez = wide ? 2 * L.nz - 1 : L.nz;
     const int cx = wide ? L.nx - 1 : 0, cy = wide ? L.ny - 1 : 0, cz = wide ? L.nz - 1 : 0;
     const size_t n = (size_t)ex * ey * ez;
     out.assign(6 * n, 0.0f);
     for (int k = 0; k < ez; ++k)
         for (int j = 0; j < ey; ++j)
             for (int i = 0; i < ex; ++i) {
+                if (i - cx > L.nx - 1 || j - cy > L.ny - 1) continue;   // padding
                 const ldbl X = i - cx, Y = j - cy, Z = k - cz;
                 const size_t o = ((size_t)k * ey + j) * ex + i;
                 out[o] = (float)(-Ms * second_differences(nwl_f, X, Y, Z));
@@ -937,11 +1016,12 @@ hipError_t dispatch_demag(sllg_ctx* C, int level, int64_t n0, int64_t ns)
     const LevelHost& h = C->lv[level];
     const int W = (int)demag_table_offsets(h.in);
     const size_t lds = 6 * sizeof(float) * (size_t)W;
+    const WideDims d = demag_wide_dims(h.in);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_demag), hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
     hipLaunchKernelGGL(k_demag, dim3((unsigned)h.ninst), dim3((unsigned)demag_block((int)h.ncell)), lds, C->stream,
                        C->d_insts, h.inst0, C->d_levels, C->d_buf0, C->d_buf1, C->d_axes, C->d_demag,
-                       demag_is_wide(h.in) ? 1 : 0, W, C->d_records, C->d_accs, C->d_ckpt, C->ckpt_every, n0, ns,
+                       demag_is_wide(h.in) ? 1 : 0, W, d.wx, d.wy, C->d_records, C->d_accs, C->d_ckpt, C->ckpt_every, n0, ns,
                        C->d_status);
     return hipGetLastError();
 }
@@ -2134,8 +2214,12 @@ int sllg_level_kernel(const sllg_ctx* C, int32_t level, char* name, int32_t cap)
     } else if (h.plan == kPlanLanes) {
         snprintf(buf, sizeof(buf), "k_lanes<%d>", kLanesThreads);
     } else if (h.plan == kPlanDemag) {
-        snprintf(buf, sizeof(buf), "k_demag %dx%d %s", demag_chunks((int)h.ncell), (int)h.ncell,
-                 demag_is_wide(h.in) ? "wide" : "octant");
+        const WideDims d = demag_wide_dims(h.in);
+        if (demag_is_wide(h.in))
+            snprintf(buf, sizeof(buf), "k_demag %dx%d wide %dx%d", demag_chunks((int)h.ncell), (int)h.ncell, d.wx,
+                     d.wy);
+        else
+            snprintf(buf, sizeof(buf), "k_demag %dx%d octant", demag_chunks((int)h.ncell), (int)h.ncell);
     } else {
         for (const auto& rs : C->res_sets)
             if (std::find(rs.levels.begin(), rs.levels.end(), level) != rs.levels.end())
