@@ -23,7 +23,10 @@
 // cells of chunk s for cell i (m_j and base(j) are one LDS broadcast, the
 // table reads run over consecutive cells), the partial sums meet in LDS and
 // the owner thread i (s = 0) adds them in chunk order and takes the Heun
-// stage.  S depends only on the cell count, so the summation order, and hence
+// stage.  While the owners take their stages the other threads are idle:
+// there, helper threads in waves without owners draw the next step's thermal
+// field (kept in LDS for the owners) and fold the previous step into the
+// loop accumulators, so neither lies on the owners' path.  S depends only on the cell count, so the summation order, and hence
 // every state, is fixed by the level.  Hd is added to the thermal field (both
 // enter the effective field as plain additive terms), so the per-cell Heun
 // functions are those of every other kernel; the field is recomputed for m'
@@ -108,8 +111,8 @@ __device__ __forceinline__ V3 demag_partial_octant(const float4* __restrict__ S,
 }
 
 // Static LDS of k_demag; the table is dynamic (6 planes of W floats).
-constexpr size_t kDemagStaticLds =
-    2 * sizeof(float4) * kDemagMaxCells + 3 * sizeof(float) * kDemagMaxThreads + 8 * (kDemagMaxThreads / 64) + 128;
+constexpr size_t kDemagStaticLds = 2 * sizeof(float4) * kDemagMaxCells + 3 * sizeof(float) * kDemagMaxThreads +
+                                   3 * sizeof(float) * kDemagMaxCells + 8 * (kDemagMaxThreads / 64) + 128;
 
 // wide != 0: the table holds every offset (W = wx wy (2nz-1) of them, rows of
 // wx, planes of wy rows); else the octant table (W = N).
@@ -127,6 +130,7 @@ __global__ __launch_bounds__(kDemagMaxThreads) void k_demag(const InstDev* __res
     __shared__ float4 A[kDemagMaxCells];          // m_n (xyz) and base(j) (w)
     __shared__ float4 B[kDemagMaxCells];          // m'
     __shared__ float P[3 * kDemagMaxThreads];     // partial sums of chunks 1 .. S-1
+    __shared__ float HT[3 * kDemagMaxCells];      // thermal field of the step (drawn by the helpers)
     __shared__ double red[kDemagMaxThreads / 64];
     __shared__ AccDev acc;                        // the loop accumulators (thread 0)
     const int inst = inst0 + static_cast<int>(blockIdx.x);
@@ -141,6 +145,12 @@ __global__ __launch_bounds__(kDemagMaxThreads) void k_demag(const InstDev* __res
     const int j0 = sums ? s * clen : 0, j1 = sums ? min(N, j0 + clen) : 0;
     const int x = sums ? i % nx : 0, y = sums ? (i / nx) % ny : 0, z = sums ? i / (nx * ny) : 0;
     // index of the cell in the wide offset grid: offset (i - j) = base(i) - base(j) + centre
+    // helpers: the threads from the first wave boundary after the owners on,
+    // one per cell, if the workgroup has that many; thread d0 also folds
+    const int d0 = (N + 63) / 64 * 64;
+    const bool helpers = d0 + N <= nthr;
+    const bool drawer = helpers && tid >= d0 && tid < d0 + N;
+    const int di = tid - d0;   // the drawer's cell
     const int basej = (z * wy + y) * wx + x;
     const int basei = ((z + nz - 1) * wy + y + ny - 1) * wx + x + nx - 1;
     const float* T = demag + L.demag_off;
@@ -191,6 +201,19 @@ __global__ __launch_bounds__(kDemagMaxThreads) void k_demag(const InstDev* __res
         }
         return h;
     };
+    auto draw = [&](int64_t n) {
+        const V3 h = thermal_field(L, I.seed, static_cast<uint32_t>(di), n);
+        HT[di] = h.x;
+        HT[N + di] = h.y;
+        HT[2 * N + di] = h.z;
+    };
+    // the loop value of step n from the wave partial sums in red
+    auto fold = [&](int64_t n) {
+        double tot = 0.0;
+        for (int k = 0; k < nthr / 64; ++k) tot += red[k];
+        loop_accumulate(acc, L, n, tot / static_cast<double>(N), rec);
+    };
+    if (drawer) draw(n0);
     float hz0 = static_cast<float>(L.hz_amp * wave_at(L, n0));
     __syncthreads();
     for (int64_t st = 0; st < nsteps; ++st) {
@@ -206,11 +229,14 @@ __global__ __launch_bounds__(kDemagMaxThreads) void k_demag(const InstDev* __res
                 cp[N + i] = m.y;
                 cp[2 * N + i] = m.z;
             }
-            hth = thermal_field(L, I.seed, static_cast<uint32_t>(i), n);
+            hth = helpers ? V3{HT[i], HT[N + i], HT[2 * N + i]} : thermal_field(L, I.seed, static_cast<uint32_t>(i), n);
             hd = total(hd);
             heun_predict(L, m, nb(A, m), u, hz0, V3{hth.x + hd.x, hth.y + hd.y, hth.z + hd.z}, mp, q);
             B[i] = make_float4(mp.x, mp.y, mp.z, wbits);
         }
+        // the previous step's loop value, off the owners' path (red is next
+        // written after the corrector)
+        if (helpers && tid == d0 && st > 0) fold(n - 1);
         __syncthreads();
         hd = partial(B);
         __syncthreads();
@@ -222,17 +248,22 @@ __global__ __launch_bounds__(kDemagMaxThreads) void k_demag(const InstDev* __res
             A[i] = make_float4(m.x, m.y, m.z, wbits);
             mz = m.z;
         }
+        // the next step's thermal field (the owners hold this step's in
+        // registers since the predictor)
+        if (drawer && st + 1 < nsteps) draw(n + 1);
         // block sum over whole waves (its barrier also ends the step: A
         // holds m_{n+1}; the next partial sums overwrite P only after it)
         const float ws = wave_sum(mz);
         if ((tid & 63) == 0) red[tid >> 6] = static_cast<double>(ws);
         __syncthreads();
-        if (tid == 0) {
-            double tot = 0.0;
-            for (int k = 0; k < nthr / 64; ++k) tot += red[k];
-            loop_accumulate(acc, L, n, tot / static_cast<double>(N), rec);
-        }
         hz0 = hz1;
+        if (!helpers) {
+            if (tid == 0) fold(n);
+            __syncthreads();
+        }
+    }
+    if (helpers) {
+        if (tid == d0 && nsteps > 0) fold(n0 + nsteps - 1);
         __syncthreads();
     }
     float* mo = (((n0 + nsteps) & 1) ? buf1 : buf0) + I.state_off;
