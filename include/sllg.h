@@ -246,7 +246,7 @@ int sllg_set_state(sllg_ctx* ctx, int32_t level, int32_t real, const float* host
  * cooperative launch in which every workgroup owns a z-slab of one
  * realization for up to 1024 steps and trades boundary planes with its two
  * neighbours through device memory each step, 4 = single-cell levels only
- * (the single-macrospin limit): one realization per lane for up to 2^20
+ * (the single-macrospin limit): one realization per quad of lanes for up to 2^20
  * steps per launch (automatic when every level of the context is a single
  * cell), 5 = with magnetostatics (material demag != 0; the only plan such a
  * level can use): one workgroup per realization, the field summed directly

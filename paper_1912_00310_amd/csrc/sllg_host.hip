@@ -998,12 +998,13 @@ hipError_t dispatch_res(sllg_ctx* C, const sllg_ctx::ResSet& rs, int64_t n0, int
 }
 
 // Single-cell levels [l0, l1) (consecutive, the same sweep position): one
-// lane per realization (a stepping and a loop wave per 64), ns steps.
+// quad of lanes per realization (four stepping waves and a loop wave per 64),
+// ns steps.
 hipError_t dispatch_lanes(sllg_ctx* C, int l0, int l1, int64_t n0, int64_t ns)
 {
     const int i0 = C->lv[l0].inst0;
     const int ni = C->lv[l1 - 1].inst0 + C->lv[l1 - 1].ninst - i0;
-    hipLaunchKernelGGL(k_lanes, dim3((unsigned)ceil_div(ni, kLanesThreads)), dim3(2 * kLanesThreads), 0, C->stream,
+    hipLaunchKernelGGL(k_lanes, dim3((unsigned)ceil_div(ni, kLanesThreads)), dim3(5 * 64), 0, C->stream,
                        C->d_insts, i0, ni, C->d_levels, C->d_buf0, C->d_buf1, C->d_axes, C->d_records, C->d_accs,
                        C->d_ckpt, C->ckpt_every, n0, ns, C->d_status);
     return hipGetLastError();

@@ -16,7 +16,7 @@ the LLG equation), i.e. to alpha at small alpha.  Hence:
     (k_B T/KV) ln(1 + alpha^2): the invariance breaks and H_c grows.
 
 ``scan`` runs each (SR, alpha) pair as its own context on its own stream
-(one realization per lane, all pairs concurrently) and returns the loops'
+(one realization per quad of lanes, all pairs concurrently) and returns the loops'
 coercive fields and areas in simulation units with their standard errors;
 ``sharrock_check`` fits the laws above.  Run
 
