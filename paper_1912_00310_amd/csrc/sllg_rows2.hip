@@ -202,7 +202,7 @@ __global__ __launch_bounds__(NT) void k_rows2(
     auto yp = [&](int i, int e) { return (e & 8) ? i + nx : i; };
 
     // The z-columns rotate with period 3 (m_n of p, p+1, p+2; axes of p-1, p,
-    // p+1; q and H_th of the plane before): the plane loop is unrolled three
+    // p+1; q and H_th of the plane before): the plane loop is unrolled six
     // times and slot (p - pz0) % 3 of each array is renamed, not copied.
     V3 M[3][K];          // m_n: slot PH = plane p, PH+1 = p+1, PH+2 = p+2
     V3 U[3][K];          // axes: slot PH = plane p-1, PH+1 = p, PH+2 = p+1
