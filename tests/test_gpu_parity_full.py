@@ -7,8 +7,9 @@ steps, the loop ordinates within 2e-6.
   * the four-level batch (1024 instances, the b = 1 level streamed, the
     others resident), 1000 steps, four realizations of every level compared;
   * the 128x128x512 block at full size, 20 steps over all 8.4M cells (the
-    oracle takes about a second per step), and a 128x128x24 slice of it for
-    1000 steps on the tile kernel the benchmark's tuner picks for the block;
+    oracle takes about a second per step), the 128x128x1024 block for 6
+    steps over all 16.8M cells, and a 128x128x24 slice of the block for 1000
+    steps on the tile kernel the benchmark's tuner picks for it;
   * the 64-realization adjoint workload (2x6x14, b = 4), 1000 steps of all 64.
 
 The oracle runs of independent realizations go to a thread pool (the C
@@ -110,6 +111,17 @@ def test_block_full_size_20_steps(P, orc):
     wl = W.workload("block_b2_cone10")
     worst, kernels = _compare_levels(P, orc, wl, [(0,)], nsteps=20, every=10)
     print(f"block 128x128x512, 20 steps on {kernels[0]}: worst |dm| = {worst:.2e}")
+
+
+def test_block_1024_planes_full_size_6_steps(P, orc):
+    # the 128x128x1024 block of the benchmark's second block leg (state and
+    # axes beyond the Infinity Cache), all 16.8M cells on the tuned tile
+    # kernel, 6 steps
+    wl = W.workload("block_b2_cone10")
+    wl["levels"][0]["nz"] = 1024
+    worst, kernels = _compare_levels(P, orc, wl, [(0,)], nsteps=6, every=3)
+    print(f"block 128x128x1024, 6 steps on {kernels[0]}: worst |dm| = {worst:.2e}")
+    assert kernels[0].startswith("k_rows2"), kernels
 
 
 def test_block_slice_1000_steps_bench_tile_kernel(P, orc):
