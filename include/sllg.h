@@ -172,7 +172,10 @@ int sllg_run_steps(sllg_ctx* ctx, int64_t nsteps);
 
 /* Wait for the context's stream and report the device status word:
  * SLLG_E_HIP if a slab exchange wait gave up, SLLG_E_NUMERIC if a loop
- * ordinate became non-finite, else SLLG_OK. */
+ * ordinate became non-finite, else SLLG_OK.  A debug build of the library
+ * (compiled with SLLG_LDS_CHECK; libsllg_ldscheck.so) also gives SLLG_E_HIP
+ * when the streamed full-width-row kernel read an LDS neighbour slot that
+ * had not been written for the plane it stands for. */
 int sllg_sync(sllg_ctx* ctx);
 
 /* Reset every level to step 0 (all cells +z, loops cleared, device status

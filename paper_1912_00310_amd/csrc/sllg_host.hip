@@ -1786,6 +1786,9 @@ int check_status(sllg_ctx* C)
         return fail(SLLG_E_HIP, "slab exchange timed out (a neighbour's boundary words did not arrive); "
                                 "the state is undefined until sllg_reset");
     if (st[0] & 1) return fail(SLLG_E_NUMERIC, "non-finite loop ordinate (the magnetisation blew up)");
+    if (st[0] & 4)
+        return fail(SLLG_E_HIP, "LDS check: a tile read a neighbour slot that was not written for its plane "
+                                "(set only by a library built with SLLG_LDS_CHECK)");
     return SLLG_OK;
 }
 

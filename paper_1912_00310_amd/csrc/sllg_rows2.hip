@@ -28,6 +28,14 @@
 // The planes z0 - 1 and z0 + nzt are predicted for the window cells only
 // (their m' is needed only as a vertical neighbour).  Workgroups are dealt to
 // the XCDs so that each XCD runs a contiguous part of the tile list.
+//
+// Built with SLLG_LDS_CHECK defined (a debug build of the library, never the
+// product), every LDS slot also carries in its fourth word the plane it
+// stands for: the slots are filled with an impossible tag at the start, each
+// write stores its plane, and each read of a neighbour or of the plane below
+// compares the tag with the plane it expects.  A mismatch (a slot read
+// before the write of its plane, or a write that never came) sets bit 4 of
+// the status word; the arithmetic is unchanged.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -39,6 +47,13 @@ namespace sllg {
 
 // third descriptor word of a raw (unformatted) buffer resource on gfx9
 constexpr int kBufDword3 = 0x00020000;
+
+#ifdef SLLG_LDS_CHECK
+constexpr bool kLdsCheck = true;
+#else
+constexpr bool kLdsCheck = false;
+#endif
+constexpr int kLdsPoison = static_cast<int>(0x80000000u);   // tag of a slot never written
 
 template <int NT, int K, bool AXES>
 __global__ __launch_bounds__(NT) void k_rows2(
@@ -93,6 +108,11 @@ __global__ __launch_bounds__(NT) void k_rows2(
     const int SP = FIXED ? NT : PC;            // stride of the m' buffers
     float4* const Mn0 = lds_rows2;             // [2][SN]: m_n of planes p and p - 1
     float4* const Mp0 = lds_rows2 + 2 * SN;    // [2][SP]: m' of planes p and p - 1
+    bool lds_bad = false;                      // debug build: a slot read with the wrong tag
+    if constexpr (kLdsCheck) {
+        for (int i = tid; i < 2 * SN + 2 * SP; i += NT) lds_rows2[i] = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(kLdsPoison));
+        __syncthreads();
+    }
     const float hz0 = static_cast<float>(L.hz_amp * wave_at(L, n));
     const float hz1 = static_cast<float>(L.hz_amp * wave_at(L, n + 1));
     const bool do_ckpt = (ckpt != nullptr) && ckpt_every > 0 && (n % ckpt_every) == 0;
@@ -188,13 +208,22 @@ __global__ __launch_bounds__(NT) void k_rows2(
     const uint32_t ex_gb = static_cast<uint32_t>(ex_gc) * 4u;
     // a cell to LDS: x, y, z of its 16-byte slot (one 12-byte store; the
     // fourth word is never read)
-    auto put = [](float4* slot, V3 v) {
+    // (the debug build also writes the plane tag into the fourth word)
+    auto put = [](float4* slot, V3 v, int plane) {
         float* q = static_cast<float*>(__builtin_assume_aligned(slot, 16));
         q[0] = v.x;
         q[1] = v.y;
         q[2] = v.z;
+        if constexpr (kLdsCheck) q[3] = __int_as_float(plane);
+        (void)plane;
     };
-    auto v34 = [](float4 v) { return V3{v.x, v.y, v.z}; };
+    // a slot's cell, read as the cell of the given plane
+    auto rd = [&](const float4* slot, int plane) {
+        const float4 v = *slot;
+        if constexpr (kLdsCheck) lds_bad = lds_bad || __float_as_int(v.w) != plane;
+        (void)plane;
+        return V3{v.x, v.y, v.z};
+    };
 
     auto xm = [&](int i, int e) { return (e & 1) ? i - 1 : i; };
     auto xp = [&](int i, int e) { return (e & 2) ? i + 1 : i; };
@@ -217,7 +246,7 @@ __global__ __launch_bounds__(NT) void k_rows2(
             // plane pz0 - 1 of the own column, the lower neighbour of the
             // first plane; at the bottom of the grid plane 0 itself, so that
             // the missing neighbour is the cell (no select in the loop)
-            put(&Mn0[SN + ii[j] + nx], ld(max(pz0 - 1, 0), gb[j]));
+            put(&Mn0[SN + ii[j] + nx], ld(max(pz0 - 1, 0), gb[j]), pz0 - 1);
         }
         M[0][j] = ld(pz0, gb[j]);
         M[1][j] = ld(pz0 + 1, gb[j]);
@@ -229,7 +258,7 @@ __global__ __launch_bounds__(NT) void k_rows2(
     }
     // the extra rows of plane p go to LDS during plane p - 1 (below), loaded
     // at the end of plane p - 3; those of the first plane here
-    if (ex) put(&Mn0[ex_li], ld(pz0, ex_gb));
+    if (ex) put(&Mn0[ex_li], ld(pz0, ex_gb), pz0);
     // extra rows of the planes p + 1, p + 2, p + 3 (slot PH holds p + 1)
     V3 E[3];
 #pragma unroll
@@ -253,7 +282,7 @@ __global__ __launch_bounds__(NT) void k_rows2(
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 if (!on[j]) continue;
-                put(&Mn[ii[j] + nx], M[PH][j]);
+                put(&Mn[ii[j] + nx], M[PH][j], p);
             }
         }
         lds_barrier();
@@ -271,20 +300,20 @@ __global__ __launch_bounds__(NT) void k_rows2(
                 // the LDS reads are issued, then the noise is drawn while they
                 // are in flight (with two cells per thread the values held
                 // meanwhile would spill)
-                const V3 n_xm = v34(Mn[xm(l, e)]), n_xp = v34(Mn[xp(l, e)]);
-                const V3 n_ym = v34(Mn[ym(l, e)]), n_yp = v34(Mn[yp(l, e)]);
+                const V3 n_xm = rd(&Mn[xm(l, e)], p), n_xp = rd(&Mn[xp(l, e)], p);
+                const V3 n_ym = rd(&Mn[ym(l, e)], p), n_yp = rd(&Mn[yp(l, e)], p);
                 // (below plane 0 the buffer holds plane 0; above nz - 1 the
                 // clamped load of M[P1] holds plane nz - 1: the cell itself)
-                const V3 n_zm = v34(Mo[l]);
+                const V3 n_zm = rd(&Mo[l], p - 1);
                 HT[PH][j] = thermal_field(Lc, I.seed, cell, n);
                 exs = nb_sum(m, n_xm, n_xp, n_ym, n_yp, n_zm, M[P1][j]);
             } else {
-                exs = nb_sum(m, v34(Mn[xm(l, e)]), v34(Mn[xp(l, e)]), v34(Mn[ym(l, e)]), v34(Mn[yp(l, e)]),
-                             v34(Mo[l]), M[P1][j]);
+                exs = nb_sum(m, rd(&Mn[xm(l, e)], p), rd(&Mn[xp(l, e)], p), rd(&Mn[ym(l, e)], p),
+                             rd(&Mn[yp(l, e)], p), rd(&Mo[l], p - 1), M[P1][j]);
                 HT[PH][j] = thermal_field(Lc, I.seed, cell, n);
             }
             heun_predict(Lc, m, exs, AXES ? U[P1][j] : u0, hz0, HT[PH][j], MP[PH][j], Q[PH][j]);
-            put(&Mp[ii[j]], MP[PH][j]);
+            put(&Mp[ii[j]], MP[PH][j], p);
         }
         // ---- the extra rows of plane p + 1 into the m_n buffer of plane
         //      p - 1, whose extra rows nobody reads after the barrier above.
@@ -292,7 +321,7 @@ __global__ __launch_bounds__(NT) void k_rows2(
         //      does not include them; the empty asm uses the loaded values in
         //      every wave, so that the wait is taken here whichever lanes store.)
         asm volatile("" ::"v"(E[PH].x), "v"(E[PH].y), "v"(E[PH].z));
-        if (ex && p + 1 <= pz1) put(&Mn0[(b ^ 1) * SN + ex_li], E[PH]);
+        if (ex && p + 1 <= pz1) put(&Mn0[(b ^ 1) * SN + ex_li], E[PH], p + 1);
         // ---- 4. corrector at plane p - 1
         const int cz = p - 1;
         if (cz >= z0 && cz < zend) {
@@ -301,12 +330,12 @@ __global__ __launch_bounds__(NT) void k_rows2(
                 if (!win[j]) continue;
                 const int i = ii[j], e = edge[j];
                 const V3 mpc = MP[P2][j];   // the own cell's m'(p - 1), also in LDS for the neighbours
-                const V3 exs = nb_sum(mpc, v34(Mq[xm(i, e)]), v34(Mq[xp(i, e)]), v34(Mq[ym(i, e)]), v34(Mq[yp(i, e)]),
-                                      cz > 0 ? MP[P1][j] : mpc, predict ? MP[PH][j] : mpc);
+                const V3 exs = nb_sum(mpc, rd(&Mq[xm(i, e)], cz), rd(&Mq[xp(i, e)], cz), rd(&Mq[ym(i, e)], cz),
+                                      rd(&Mq[yp(i, e)], cz), cz > 0 ? MP[P1][j] : mpc, predict ? MP[PH][j] : mpc);
                 const V3 mn1 = heun_correct(Lc, mpc, exs, AXES ? U[PH][j] : u0, hz1, HT[P2][j], Q[P2][j]);
                 st3(r_out, cz, gb[j], mn1);
                 msum += mn1.z;
-                if (do_ckpt) st3(r_ck, cz, gb[j], v34(Mo[ii[j] + nx]));
+                if (do_ckpt) st3(r_ck, cz, gb[j], rd(&Mo[ii[j] + nx], cz));
             }
         }
         // ---- 5. loads of the extra rows of plane p + 4 into their slot of
@@ -340,6 +369,8 @@ __global__ __launch_bounds__(NT) void k_rows2(
         plane(std::integral_constant<int, 5>{}, p + 5);
     }
 
+    if constexpr (kLdsCheck)
+        if (lds_bad) atomicOr(status, 4);
     const double tot = block_sum<NT>(msum, red);
     stream_block_end(tot, n, tile, ptiles, partials, first_tile, pend, T.inst, launch_cnt, steps, I.level,
                      L.n_steps);

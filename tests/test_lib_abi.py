@@ -35,6 +35,16 @@ def test_every_declared_symbol_is_exported(L):
     assert sorted(L.exported_symbols()) == names
 
 
+def test_debug_library_exports_the_same_symbols(L):
+    # the LDS-check build (tests only) has the product library's C ABI
+    from paper_1912_00310_amd import build_debug
+    if not os.path.exists(build_debug.LIB):
+        build_debug.build()
+    lib = C.CDLL(build_debug.LIB)
+    for n in header_functions():
+        assert hasattr(lib, n), n
+
+
 def test_workspace_bytes_sizes(L):
     wl = W.workload("rod_b4_single")
     m = L.material_struct(wl["material"])
