@@ -34,11 +34,12 @@ CASES = {
     # ragged z tiles (10 + 10 + 4), one and two cells per thread
     "rows2_block_slice_1024x1": dict(wl="block_b2_cone10", level=dict(nz=24), stream=(2, 1024, 1, 1, 10), steps=6),
     "rows2_block_slice_1024x2": dict(wl="block_b2_cone10", level=dict(nz=24), stream=(2, 1024, 2, 1, 8), steps=6),
-    # ragged row windows and tiles at both grid ends, small grids
+    # ragged row windows and tiles at both grid ends, small grids (the second
+    # one long enough for graph replays of 8 .. 128 launches)
     "rows2_ragged_512x2": dict(wl="block_b2_cone10", level=dict(nx=40, ny=36, nz=20), stream=(2, 512, 2, 1, 7),
                                steps=6),
     "rows2_ragged_256x1": dict(wl="block_b2_cone10", level=dict(nx=32, ny=50, nz=17), stream=(2, 256, 1, 1, 5),
-                               steps=6),
+                               steps=300),
     # one easy axis for all cells (no per-cell axes), two realizations,
     # checkpoints every 2 steps (the checkpoint path reads LDS too; a fast
     # sweep keeps the checkpoints of the whole sweep small)
@@ -70,8 +71,15 @@ def workload(c):
     return wl
 
 
-def run_case(P, name):
-    """(status, digest, kernel) of one case with the package's library."""
+def pieces(steps):
+    """The case's steps in three runs: 1, about a third, the rest."""
+    a = max(1, steps // 3)
+    return [1, a, steps - 1 - a]
+
+
+def run_case(P, name, split=False):
+    """(status, digest, kernel) of one case with the package's library; with
+    split, the steps are run in three calls (pieces) instead of one."""
     c = CASES[name]
     wl = workload(c)
     sim = P.Sim(wl["material"], wl["levels"], ckpt_every=c.get("ckpt", 0))
@@ -85,7 +93,8 @@ def run_case(P, name):
                 sim.set_slab_shape(0, *c["slab"])
         except P.SllgError:
             return "refused", None, None
-        sim.run_steps(c["steps"])
+        for k in (pieces(c["steps"]) if split else [c["steps"]]):
+            sim.run_steps(k)
         sim.synchronize()
         h = hashlib.sha256()
         for r in range(wl["levels"][0]["n_real"]):

@@ -11,6 +11,10 @@
   * Run twice: every plan and tile kernel, run twice from the same seeds in
     fresh contexts, gives bit-identical states and loop ordinates (a race
     between the threads of a kernel shows as a run-to-run difference).
+  * Split runs: every case run in three calls (1 step, about a third, the
+    rest) gives the bits of one call: the step index alone fixes the noise,
+    and the launch units (graph replays, slab and resident launches) may be
+    cut anywhere.
   * Launch-blocking mode: a child process with every launch synchronous
     (HIP_LAUNCH_BLOCKING=1, kernels and copies serialised) gives the same
     bits as the normal asynchronous run, on every plan but the slab plan
@@ -85,6 +89,15 @@ def test_run_twice_bit_identical(P, reference):
     for name in G.CASES:
         status, digest, kernel = G.run_case(P, name)
         print(name, kernel, flush=True)
+        assert status == "ok", (name, status)
+        assert digest == reference[name][1], name
+
+
+def test_split_runs_bit_identical(P, reference):
+    for name in G.CASES:
+        assert sum(G.pieces(G.CASES[name]["steps"])) == G.CASES[name]["steps"]
+        status, digest, kernel = G.run_case(P, name, split=True)
+        print(name, kernel, G.pieces(G.CASES[name]["steps"]), flush=True)
         assert status == "ok", (name, status)
         assert digest == reference[name][1], name
 
