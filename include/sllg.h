@@ -244,6 +244,25 @@ int sllg_get_state(sllg_ctx* ctx, int32_t level, int32_t real, float* host_m);
  * planes mx | my | mz; vectors are used as given). */
 int sllg_set_state(sllg_ctx* ctx, int32_t level, int32_t real, const float* host_m);
 
+/* Checkpoint and resume of a sweep (the counter-based noise needs only the
+ * step index, so no generator state is kept).  sllg_save_state waits for the
+ * context's stream and copies everything a sweep carries from one step to
+ * the next into host memory: every level's step index, both magnetisation
+ * buffers, the FP64 loop accumulators and crossing state, the loop records,
+ * the adjoint checkpoints and the device status word.  *need receives the
+ * snapshot's size; with host == NULL only the size is returned; cap < *need
+ * gives SLLG_E_INVAL; a context whose status word reports a failure is not
+ * saved (its error is returned).  The caller owns the buffer; the format is
+ * private to this library version.  sllg_load_state puts a snapshot into a
+ * context created from the same material, levels and checkpoint interval
+ * (grids, seeds, compiled constants and buffer sizes must match, else
+ * SLLG_E_INVAL and the context is unchanged); plans and tile shapes may
+ * differ, since they all give the same bits.  Continuing from a loaded
+ * snapshot gives the states and loops of the uninterrupted run bit for bit.
+ * Both synchronise the stream. */
+int sllg_save_state(sllg_ctx* ctx, void* host, size_t cap, size_t* need);
+int sllg_load_state(sllg_ctx* ctx, const void* host, size_t size);
+
 /* Execution plan of a level: 0 = automatic, 1 = LDS-resident persistent
  * kernel, 2 = one fused launch per step over tiles, 3 = persistent
  * cooperative launch in which every workgroup owns a z-slab of one

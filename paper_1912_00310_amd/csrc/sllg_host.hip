@@ -1794,6 +1794,64 @@ int check_status(sllg_ctx* C)
 
 }  // namespace
 
+// ---- snapshots: the state a sweep carries from one step to the next ----
+// Layout (host bytes): SnapHead, one SnapLevel per level, the device status
+// word (4 ints), the step indices, both state buffers, the loop
+// accumulators, the loop records and the checkpoints.  Everything else in the
+// workspace is either rebuilt by sllg_init (tables, axes) or empty between
+// runs (pending folds, launch counters, exchange words, partial sums).
+namespace {
+constexpr char kSnapMagic[8] = {'S', 'L', 'L', 'G', 'S', 'N', 'P', '1'};
+struct SnapHead {
+    char magic[8];
+    int32_t nlev, ckpt_every;
+    int64_t state_floats, rec_doubles, ckpt_floats, ninst;
+};
+struct SnapLevel {
+    int32_t nx, ny, nz, n_real;
+    uint64_t seed_base, axis_seed;
+    int64_t n_steps, step;
+    double dt, sigma, c_ex, hk, alpha, hz_amp;
+};
+SnapLevel snap_level(const LevelHost& h)
+{
+    SnapLevel s{};
+    s.nx = h.in.nx;
+    s.ny = h.in.ny;
+    s.nz = h.in.nz;
+    s.n_real = h.in.n_real;
+    s.seed_base = h.in.seed_base;
+    s.axis_seed = h.in.axis_seed;
+    s.n_steps = h.n_steps;
+    s.step = h.step;
+    s.dt = h.dt;
+    s.sigma = h.sigma;
+    s.c_ex = h.c_ex;
+    s.hk = h.hk;
+    s.alpha = h.alpha;
+    s.hz_amp = h.hz_amp;
+    return s;
+}
+// the device regions of a snapshot, in order
+std::vector<std::pair<void*, size_t>> snap_regions(const sllg_ctx* C)
+{
+    const Layout& L = C->lay;
+    return {{C->d_status, sizeof(int) * 4},
+            {C->d_steps, sizeof(int64_t) * C->lv.size()},
+            {C->d_buf0, sizeof(float) * (size_t)L.state_floats},
+            {C->d_buf1, sizeof(float) * (size_t)L.state_floats},
+            {C->d_accs, sizeof(AccDev) * (size_t)L.ninst_total},
+            {C->d_records, sizeof(double) * (size_t)L.rec_doubles},
+            {C->d_ckpt, sizeof(float) * (size_t)L.ckpt_floats}};
+}
+size_t snap_bytes(const sllg_ctx* C)
+{
+    size_t n = sizeof(SnapHead) + sizeof(SnapLevel) * C->lv.size();
+    for (const auto& r : snap_regions(C)) n += r.second;
+    return n;
+}
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -2248,6 +2306,75 @@ int sllg_get_state(sllg_ctx* C, int32_t level, int32_t real, float* host_m)
     const float* src = ((h.step & 1) ? C->d_buf1 : C->d_buf0) + I.state_off;
     HIP_OK(hipMemcpyAsync(host_m, src, sizeof(float) * 3 * h.ncell, hipMemcpyDeviceToHost, C->stream));
     return check_status(C);
+}
+
+int sllg_save_state(sllg_ctx* C, void* host, size_t cap, size_t* need)
+{
+    if (!C || !need) return fail(SLLG_E_INVAL, "bad args");
+    *need = snap_bytes(C);
+    if (!host) return SLLG_OK;
+    if (cap < *need) return fail(SLLG_E_INVAL, "snapshot buffer of %zu bytes, %zu needed", cap, *need);
+    // every enqueued step has finished (and folded) once the stream is idle;
+    // a failed run is not saved
+    const int rc = check_status(C);
+    if (rc) return rc;
+    char* p = static_cast<char*>(host);
+    SnapHead hd{};
+    std::memcpy(hd.magic, kSnapMagic, sizeof(hd.magic));
+    hd.nlev = (int32_t)C->lv.size();
+    hd.ckpt_every = C->ckpt_every;
+    hd.state_floats = C->lay.state_floats;
+    hd.rec_doubles = C->lay.rec_doubles;
+    hd.ckpt_floats = C->lay.ckpt_floats;
+    hd.ninst = C->lay.ninst_total;
+    std::memcpy(p, &hd, sizeof(hd));
+    p += sizeof(hd);
+    for (const LevelHost& h : C->lv) {
+        const SnapLevel sl = snap_level(h);
+        std::memcpy(p, &sl, sizeof(sl));
+        p += sizeof(sl);
+    }
+    for (const auto& r : snap_regions(C)) {
+        if (r.second) HIP_OK(hipMemcpyAsync(p, r.first, r.second, hipMemcpyDeviceToHost, C->stream));
+        p += r.second;
+    }
+    HIP_OK(hipStreamSynchronize(C->stream));
+    return SLLG_OK;
+}
+
+int sllg_load_state(sllg_ctx* C, const void* host, size_t size)
+{
+    if (!C || !host) return fail(SLLG_E_INVAL, "bad args");
+    if (size != snap_bytes(C))
+        return fail(SLLG_E_INVAL, "snapshot of %zu bytes; this context's snapshots have %zu", size, snap_bytes(C));
+    const char* p = static_cast<const char*>(host);
+    SnapHead hd;
+    std::memcpy(&hd, p, sizeof(hd));
+    p += sizeof(hd);
+    if (std::memcmp(hd.magic, kSnapMagic, sizeof(hd.magic)) != 0) return fail(SLLG_E_INVAL, "not a snapshot");
+    if (hd.nlev != (int32_t)C->lv.size() || hd.ckpt_every != C->ckpt_every ||
+        hd.state_floats != C->lay.state_floats || hd.rec_doubles != C->lay.rec_doubles ||
+        hd.ckpt_floats != C->lay.ckpt_floats || hd.ninst != C->lay.ninst_total)
+        return fail(SLLG_E_INVAL, "snapshot of another configuration (levels, sizes or checkpoint interval)");
+    std::vector<SnapLevel> sl(C->lv.size());
+    for (size_t l = 0; l < C->lv.size(); ++l) {
+        std::memcpy(&sl[l], p, sizeof(SnapLevel));
+        p += sizeof(SnapLevel);
+        SnapLevel mine = snap_level(C->lv[l]);
+        mine.step = sl[l].step;
+        if (std::memcmp(&mine, &sl[l], sizeof(SnapLevel)) != 0)
+            return fail(SLLG_E_INVAL, "snapshot of another configuration (level %zu: grid, seeds or constants)", l);
+        if (sl[l].step < 0 || sl[l].step > sl[l].n_steps) return fail(SLLG_E_INVAL, "snapshot step out of range");
+    }
+    // nothing of this context may still be running while its state is replaced
+    HIP_OK(hipStreamSynchronize(C->stream));
+    for (const auto& r : snap_regions(C)) {
+        if (r.second) HIP_OK(hipMemcpyAsync(r.first, p, r.second, hipMemcpyHostToDevice, C->stream));
+        p += r.second;
+    }
+    HIP_OK(hipStreamSynchronize(C->stream));
+    for (size_t l = 0; l < C->lv.size(); ++l) C->lv[l].step = sl[l].step;
+    return SLLG_OK;
 }
 
 int sllg_set_state(sllg_ctx* C, int32_t level, int32_t real, const float* host_m)

@@ -89,6 +89,8 @@ def lib():
             "sllg_get_state": (C.c_int, [vp, C.c_int32, C.c_int32, P(C.c_float)]),
             "sllg_set_state": (C.c_int, [vp, C.c_int32, C.c_int32, P(C.c_float)]),
             "sllg_set_plan": (C.c_int, [vp, C.c_int32, C.c_int32]),
+            "sllg_save_state": (C.c_int, [vp, vp, C.c_size_t, P(C.c_size_t)]),
+            "sllg_load_state": (C.c_int, [vp, vp, C.c_size_t]),
             "sllg_set_slab_shape": (C.c_int, [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
             "sllg_set_stream_shape": (C.c_int, [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                                 C.c_int32]),
@@ -118,7 +120,8 @@ def exported_symbols():
         "sllg_level_step", "sllg_level_kernel", "sllg_get_state", "sllg_set_state", "sllg_set_plan",
         "sllg_set_slab_shape", "sllg_set_stream_shape",
         "sllg_philox_probe", "sllg_get_axes", "sllg_set_timing", "sllg_kernel_time",
-        "sllg_sync", "sllg_set_options", "sllg_set_spin_limit", "sllg_init_static")]
+        "sllg_sync", "sllg_set_options", "sllg_set_spin_limit", "sllg_init_static", "sllg_save_state",
+        "sllg_load_state")]
 
 
 def _check(fn, rc):
@@ -279,6 +282,19 @@ class Sim:
         a = np.ascontiguousarray(np.asarray(m, dtype=np.float32).reshape(3, -1))
         _check("sllg_set_state", lib().sllg_set_state(self.ctx, level, real,
                                                       a.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def save_state(self) -> bytes:
+        """Snapshot of everything the sweep carries from step to step (step
+        indices, magnetisation, loop accumulators and records, checkpoints)."""
+        need = C.c_size_t()
+        _check("sllg_save_state", lib().sllg_save_state(self.ctx, None, 0, C.byref(need)))
+        buf = C.create_string_buffer(need.value)
+        _check("sllg_save_state", lib().sllg_save_state(self.ctx, buf, need.value, C.byref(need)))
+        return buf.raw
+
+    def load_state(self, snap: bytes):
+        """Continue from a snapshot of a context of the same configuration."""
+        _check("sllg_load_state", lib().sllg_load_state(self.ctx, snap, len(snap)))
 
     def set_plan(self, level: int, plan: int):
         _check("sllg_set_plan", lib().sllg_set_plan(self.ctx, level, plan))

@@ -77,24 +77,51 @@ def pieces(steps):
     return [1, a, steps - 1 - a]
 
 
-def run_case(P, name, split=False):
-    """(status, digest, kernel) of one case with the package's library; with
-    split, the steps are run in three calls (pieces) instead of one."""
+def open_case(P, name):
+    """A fresh context of the case, on its plan or tile shape."""
     c = CASES[name]
     wl = workload(c)
     sim = P.Sim(wl["material"], wl["levels"], ckpt_every=c.get("ckpt", 0))
     try:
-        try:
-            if "plan" in c:
-                sim.set_plan(0, getattr(P, c["plan"]))
-            if "stream" in c:
-                sim.set_stream_shape(0, *c["stream"])
-            if "slab" in c:
-                sim.set_slab_shape(0, *c["slab"])
-        except P.SllgError:
+        if "plan" in c:
+            sim.set_plan(0, getattr(P, c["plan"]))
+        if "stream" in c:
+            sim.set_stream_shape(0, *c["stream"])
+        if "slab" in c:
+            sim.set_slab_shape(0, *c["slab"])
+    except P.SllgError:
+        sim.close()
+        return None
+    return sim
+
+
+def run_case(P, name, split=False, resume=False):
+    """(status, digest, kernel) of one case with the package's library; with
+    split, the steps are run in three calls (pieces) instead of one; with
+    resume, the first two pieces run in one context, whose snapshot a second
+    context loads and continues."""
+    c = CASES[name]
+    wl = workload(c)
+    if resume:
+        first = open_case(P, name)
+        if first is None:
             return "refused", None, None
-        for k in (pieces(c["steps"]) if split else [c["steps"]]):
-            sim.run_steps(k)
+        try:
+            for k in pieces(c["steps"])[:2]:
+                first.run_steps(k)
+            snap = first.save_state()
+        finally:
+            first.close()
+    sim = open_case(P, name)
+    if sim is None:
+        return "refused", None, None
+    try:
+        if resume:
+            sim.load_state(snap)
+            sim.run_steps(pieces(c["steps"])[2])
+        else:
+            for k in (pieces(c["steps"]) if split else [c["steps"]]):
+                sim.run_steps(k)
         sim.synchronize()
         h = hashlib.sha256()
         for r in range(wl["levels"][0]["n_real"]):

@@ -15,6 +15,10 @@
     rest) gives the bits of one call: the step index alone fixes the noise,
     and the launch units (graph replays, slab and resident launches) may be
     cut anywhere.
+  * Resume: the first two pieces in one context, its snapshot
+    (sllg_save_state) loaded into a fresh context (sllg_load_state), the
+    rest there: the bits of the uninterrupted run, on every plan; a snapshot
+    of another configuration or of the wrong size is refused.
   * Launch-blocking mode: a child process with every launch synchronous
     (HIP_LAUNCH_BLOCKING=1, kernels and copies serialised) gives the same
     bits as the normal asynchronous run, on every plan but the slab plan
@@ -100,6 +104,36 @@ def test_split_runs_bit_identical(P, reference):
         print(name, kernel, G.pieces(G.CASES[name]["steps"]), flush=True)
         assert status == "ok", (name, status)
         assert digest == reference[name][1], name
+
+
+def test_resume_from_snapshot_bit_identical(P, reference):
+    for name in G.CASES:
+        status, digest, kernel = G.run_case(P, name, resume=True)
+        print(name, kernel, flush=True)
+        assert status == "ok", (name, status)
+        assert digest == reference[name][1], name
+
+
+def test_snapshot_of_another_configuration_is_refused(P):
+    a = G.open_case(P, "resident_rod_b4")
+    a.run_steps(10)
+    snap = a.save_state()
+    before = a.get_state(0, 0)
+    with pytest.raises(P.SllgError):
+        a.load_state(snap[:-8])          # wrong size
+    bad = bytearray(snap)
+    bad[0] ^= 0xFF
+    with pytest.raises(P.SllgError):
+        a.load_state(bytes(bad))         # not a snapshot
+    assert (a.get_state(0, 0) == before).all()
+    a.close()
+    wl = G.workload(G.CASES["resident_rod_b4"])
+    wl["levels"][0]["seed_base"] += 1    # same sizes, other seeds
+    b = P.Sim(wl["material"], wl["levels"])
+    with pytest.raises(P.SllgError):
+        b.load_state(snap)
+    assert b.step(0) == 0
+    b.close()
 
 
 def test_launch_blocking_mode_bit_identical(reference):
