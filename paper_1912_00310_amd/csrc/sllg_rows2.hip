@@ -34,8 +34,8 @@
 // stands for: the slots are filled with an impossible tag at the start, each
 // write stores its plane, and each read of a neighbour or of the plane below
 // compares the tag with the plane it expects.  A mismatch (a slot read
-// before the write of its plane, or a write that never came) sets bit 4 of
-// the status word; the arithmetic is unchanged.
+// before the write of its plane, or a write that never came) sets bit 2
+// (value 4) of the status word; the arithmetic is unchanged.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
