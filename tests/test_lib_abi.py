@@ -45,6 +45,14 @@ def test_debug_library_exports_the_same_symbols(L):
         assert hasattr(lib, n), n
 
 
+def test_snapshot_calls_reject_null_arguments(L):
+    # argument checks come before any device access
+    need = C.c_size_t(7)
+    assert L.lib().sllg_save_state(None, None, 0, C.byref(need)) == -1
+    assert L.lib().sllg_load_state(None, b"x", 1) == -1
+    assert L.lib().sllg_last_error()
+
+
 def test_workspace_bytes_sizes(L):
     wl = W.workload("rod_b4_single")
     m = L.material_struct(wl["material"])
